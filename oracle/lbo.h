@@ -1,0 +1,112 @@
+/*
+ * lbo.h -- C interface of the reference oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * A plain, serial, FP64 CPU implementation of one time step of the LBsoft
+ * two-component lattice-BGK fluid coupled to rigid colloidal spheres
+ * (Bonaccorso et al., "LBsoft: a parallel open-source software for simulation
+ * of colloidal systems", Sec. 2 and the eight-step sequence of Sec. 3.1).
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library. It shares no code, header, table or
+ * constant with the HIP implementation and must never be used as a fallback
+ * for it.
+ *
+ * Conventions
+ *   node index       n = x + nx*(y + ny*z)
+ *   populations      [k][i][n] (component, oracle direction order, node), FP64,
+ *                    full values f_i (not deviations); solid nodes hold 0
+ *   direction order  the oracle's own, returned by lbo_lattice()
+ *   owner map        0 = fluid, p+1 = solid node of particle p, -1 = wall
+ */
+#ifndef LBO_H
+#define LBO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBO_OK = 0,
+  LBO_E_ARG = -1,      /* invalid parameter                                   */
+  LBO_E_SPEED = -6     /* a particle moved more than half a node in one step  */
+};
+
+typedef struct lbo_params {
+  int32_t nx, ny, nz;
+  int32_t walls;            /* 0: periodic in z; 1: solid layers z=0 and z=nz-1 */
+  double  wall_u_lo[3];     /* velocity of the z=0 wall layer                   */
+  double  wall_u_hi[3];     /* velocity of the z=nz-1 wall layer                */
+  int32_t ncomp;            /* 1 or 2 fluid components                          */
+  double  tau[2];           /* BGK relaxation times                             */
+  double  G;                /* Shan-Chen inter-component coupling               */
+  double  sc_norm;          /* stencil normalisation of the Shan-Chen sum       */
+  double  g[3];             /* body acceleration (force density rho_k * g)      */
+  double  radius;           /* sphere radius R                                  */
+  double  particle_density; /* mass m = density * 4/3 pi R^3                    */
+  double  hertz_K, hertz_d0, hertz_rcap;
+  double  zeta[2];          /* wetting constants of the virtual solid density   */
+  double  rho_fallback[2];  /* density of a created node with no fluid neighbour */
+  int32_t rotate;           /* integrate the rotational degrees of freedom      */
+  int32_t particles_fixed;  /* spheres are static obstacles: no map updates,
+                               no pair forces, no integration                  */
+} lbo_params;
+
+/* per-particle record returned by lbo_get_particles, in this order */
+#define LBO_PREC 50
+/*  0 x[3]  3 v[3] (t-1/2)  6 w[3] (t-1/2)  9 q[4]
+ * 13 Fliq_prev[3]  16 Tliq_prev[3]
+ * last completed step:  19 Fd[3] 22 Td[3] 25 Fc[3] 28 Tc[3] 31 FH[3]
+ *                       34 FSC[3] 37 TSC[3] 40 Fliq[3] 43 Tliq[3]
+ * 46 sum over links of |F_link|   47 mass  48 inertia
+ * 49 1 when Fliq_prev/Tliq_prev hold a previous half-step value, else 0 */
+
+/* observables, lbo_observables() */
+#define LBO_NOBS 32
+/*  0 mass A   1 mass B   2..4 bare fluid momentum sum_k j_k
+ *  5 rho min A  6 rho min B  7 rho max A  8 rho max B  9 max |u|
+ * 10 fluid node count  11..13 particle momentum  14 particle KE (transl.)
+ * 15 particle KE (rot.)
+ * ledger of the last completed step:
+ * 16,17 mass removed by destroyed nodes (A,B)  18,19 mass added by created nodes
+ * 20,21 mass change from the moving-link corrections (A,B)
+ * 22..24 body force sum_n sum_k rho_k g on the fluid nodes after the map update
+ * 25..27 Shan-Chen force summed over fluid nodes
+ * 28..30 link force sum_links F_link over wall links   31 step counter */
+
+void*   lbo_create(const lbo_params* p, const double* rho0 /* [ncomp][N] */,
+                   const double* u0 /* [N][3] or NULL */);
+void    lbo_destroy(void* s);
+int     lbo_add_particles(void* s, int32_t n, const double* x, const double* v,
+                          const double* w, const double* q);
+int     lbo_step(void* s, int32_t nsteps);
+void    lbo_lattice(int32_t* c /* [19][3] */, double* w /* [19] */);
+void    lbo_get_f(const void* s, double* f);
+void    lbo_set_f(void* s, const double* f);
+void    lbo_get_rho(const void* s, double* rho /* [ncomp][N] */);
+void    lbo_get_u(const void* s, double* u /* [N][3] */);
+void    lbo_get_owner(const void* s, int32_t* owner);
+void    lbo_set_owner(void* s, const int32_t* owner);
+int32_t lbo_num_particles(const void* s);
+void    lbo_get_particles(const void* s, double* out /* [P][LBO_PREC] */);
+void    lbo_set_particle_state(void* s, const double* in /* [P][LBO_PREC] */);
+void    lbo_observables(const void* s, double* out /* [LBO_NOBS] */);
+double  lbo_loss(const void* s);
+
+/* Test hook: apply nsteps of the rotational update to q at constant w. */
+void    lbo_test_rotate(double* q /* [4] */, const double* w /* [3] */, int32_t nsteps);
+
+/* Forward-mode (dual number) run from the initial state f = f_eq(rho0, 0):
+ * returns L after nsteps and the directional derivative
+ *   dL = dL/dG * dG + dL/dg . dg + sum_n dL/drho0_A(n) * drhoA(n).
+ * Particles (optional) are static obstacles; requires particles_fixed = 1
+ * when np > 0. */
+int     lbo_loss_tangent(const lbo_params* p, const double* rho0, int32_t np,
+                         const double* x, int32_t nsteps, double dG,
+                         const double* dg /* [3] */, const double* drhoA /* [N] or NULL */,
+                         double* L, double* dL);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
