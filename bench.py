@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the two-fluid + colloid D3Q19 step on one MI355X.
+
+Default workload: a 512^3 periodic box, two Shan-Chen components (tau = 1,
+G = 0.65, rho_k = 1 + 0.01 (2U - 1) per node) and 32,000 moving spheres of
+radius 5.5 placed at random without overlap (16.6% solids), FP32 deviation
+storage. Inputs are seeded and synthetic (no dataset is involved).
+
+Prints one JSON line: MLUPS (all nodes counted, paper's Eq. glups), the
+roofline of the dominant kernel (collide-stream-bounce-back) from its own
+HIP-event time, the FP64 path's MLUPS on the same workload, and the serial
+oracle's MLUPS on a bounded sample of the workload (CPU baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q19 two-fluid+colloid MLUPS & % HBM peak, FP32 vs FP64 at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def params_for(w, precision):
+    from paper_2004_04080_amd import Params
+    return Params(w.nx, w.ny, w.nz, ncomp=w.ncomp, tau=w.tau, G=w.G, precision=precision,
+                  walls=w.walls, wall_u_lo=w.wall_u_lo, wall_u_hi=w.wall_u_hi, g=w.g,
+                  max_particles=w.nparticles, radius=w.radius,
+                  particle_density=w.particle_density, hertz_K=w.hertz_K,
+                  particles_fixed=w.particles_fixed)
+
+
+def link_count(owner: np.ndarray, shape) -> tuple:
+    """(fluid nodes, links from a fluid node to a solid neighbour) of a map."""
+    nx, ny, nz = shape
+    solid = (owner != 0).reshape(nz, ny, nx)
+    fluid = ~solid
+    links = 0
+    for cx in (-1, 0, 1):
+        for cy in (-1, 0, 1):
+            for cz in (-1, 0, 1):
+                if (cx, cy, cz) == (0, 0, 0) or abs(cx) + abs(cy) + abs(cz) > 2:
+                    continue
+                nb = np.roll(solid, shift=(-cz, -cy, -cx), axis=(0, 1, 2))
+                links += int(np.count_nonzero(fluid & nb))
+    return int(np.count_nonzero(fluid)), links
+
+
+def run_gpu(w, rho, x, precision, steps, warmup, want_roofline):
+    import torch
+    from paper_2004_04080_amd import Lattice
+    t0 = time.time()
+    lat = Lattice(params_for(w, precision), rho)
+    if len(x):
+        lat.add_particles(x)
+    log(f"[bench] {w.name} {precision}: state on the GPU after {time.time() - t0:.1f}s")
+    lat.step(warmup)
+    lat.sync()
+    log(f"[bench] {w.name} {precision}: {warmup} warm-up steps done")
+    lat.timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    phases = lat.timing_read()
+    lat.timing(False)
+    obs = lat.observables(raise_on_flag=False)
+    log(f"[bench] {w.name} {precision}: {steps} steps in {ms:.1f} ms; phases {phases}")
+    out = dict(ms_per_step=ms / steps, mlups=w.N * steps / (ms * 1e-3) / 1e6, phases=phases,
+               flags=obs.flags, mass=obs.mass.tolist())
+    if want_roofline:
+        nfl, nlinks = link_count(lat.owner(), (w.nx, w.ny, w.nz))
+        out["fluid_nodes"] = nfl
+        out["links"] = nlinks
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline(w, res, es):
+    """Algorithmic bytes of one collide launch over its average duration."""
+    K = w.ncomp
+    nfl, nlinks, N = res["fluid_nodes"], res["links"], w.N
+    bytes_launch = (nfl * 2 * K * 19 * es      # gather + store of the populations
+                    + N * K * es               # pseudo-potential field, read once
+                    + N * 2                    # owner map
+                    + nlinks * K * es)         # reflected values written into solid slots
+    ms, n = res["phases"]["collide"]
+    avg_ms = ms / max(n, 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_collide", "bytes_per_launch": bytes_launch,
+            "avg_launch_ms": round(avg_ms, 4)}
+
+
+def cpu_baseline():
+    """The serial FP64 oracle on a bounded sample of the workload: a 128^3 box
+    with the same fluid parameters and sphere volume fraction (500 spheres of
+    radius 5.5), timed over 2 steps on one host thread."""
+    import oracle as O
+    import synth
+    w = synth.workload("C3")
+    p = O.Params(w.nx, w.ny, w.nz, ncomp=2, tau=w.tau, G=w.G, radius=w.radius,
+                 particle_density=w.particle_density, hertz_K=w.hertz_K)
+    o = O.Oracle(p, w.densities())
+    o.add_particles(w.centres())
+    t = time.time()
+    steps = 2
+    o.step(steps)
+    dt = time.time() - t
+    return {"value": round(w.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} steps of a 128^3 two-fluid box with 500 spheres R=5.5 "
+                      f"(same fluid parameters and volume fraction), {dt:.1f}s serial FP64"}
+
+
+def copy_probe(gib: float, reps: int = 5) -> dict:
+    """A plain device-to-device copy of known size: the measured copy bandwidth,
+    and the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = int(gib * (1 << 30))
+    a = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"copy_bytes_read": n, "copy_bytes_written": n, "ms": round(ms, 4),
+            "GBps_read_plus_write": round(2 * n / (ms * 1e-3) / 1e9, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="T")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB and report it")
+    args = ap.parse_args()
+    if args.copy_probe > 0:
+        print(json.dumps(copy_probe(args.copy_probe)), flush=True)
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the slab decomposition over RCCL is a design, not code). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import synth
+    w = synth.workload(args.workload)
+    es = 4 if args.precision == "fp32" else 8
+    t0 = time.time()
+    rho = w.densities()
+    x = w.centres()
+    log(f"[bench] {w.name}: seeded inputs ready in {time.time() - t0:.1f}s")
+    res = run_gpu(w, rho, x, args.precision, args.steps, args.warmup, want_roofline=True)
+    fp64 = None
+    if not args.no_fp64 and args.precision == "fp32":
+        r64 = run_gpu(w, rho, x, "fp64", args.fp64_steps, 2, want_roofline=False)
+        fp64 = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "steps": args.fp64_steps,
+                "ms_per_step": round(r64["ms_per_step"], 3)}
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    line = {
+        "metric": METRIC,
+        "value": round(res["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} two-fluid Shan-Chen D3Q19 "
+                               f"(tau=1, G=0.65) + {w.nparticles} moving spheres R={w.radius}",
+                   "nodes": w.N, "spheres": w.nparticles,
+                   "fluid_nodes": res["fluid_nodes"], "links": res["links"]},
+        "roofline": roofline(w, res, es),
+        "cpu_baseline": cpu,
+        "fp64": fp64,
+        "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)
+                               for k, v in res["phases"].items()},
+        "flags": res["flags"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * lbhip.h -- C interface of the MI355X (gfx950) implementation of the LBsoft
+ * two-component lattice-Boltzmann + colloid time step.
+ *
+ * Method: Bonaccorso et al., "LBsoft: a parallel open-source software for
+ * simulation of colloidal systems" (arXiv 2004.04080). One call of lb_step
+ * advances the state by the eight-step particle sequence of Sec. 3.1:
+ * moments (Eq. rho, vel, scvel), fluid-node destruction and creation
+ * (Eq. distr, creat), Hertz contacts (Eq. hertzpot), virtual solid densities
+ * and Shan-Chen forces (Eq. soliddens, shanchen, shanchen2), the EDM collision
+ * (Eq. lbsbgk), moving halfway bounce-back with link momentum exchange
+ * (Eq. LADDFLBE, UPI, LADDFORCE, FORCEPARTEQ, TORQUEPARTEQ), the rotational
+ * leap-frog of the spheres (Eq. lf, quatder, svanimpl) and streaming (Eq. bgk2).
+ *
+ * Conventions
+ *  - Node index n = x + nx*(y + ny*z); lattice units throughout.
+ *  - Populations travel across the interface only as FP64 "post-streaming"
+ *    values f^k_i(n, t) on fluid nodes, layout [k][i][n], direction order of
+ *    lb_lattice(). Inside the library they are stored in FP32 or FP64 as
+ *    deviations f_i - w_i rho0_k from the lattice weights.
+ *  - Device buffers are allocated and owned by the caller (sizes from
+ *    lb_required_sizes) and must outlive the context; the library never
+ *    frees them. All device work is queued on the stream given to lb_init;
+ *    calls marked "synchronises" wait for that stream.
+ *  - Every call returns an lb_status (0 = success, < 0 = error); nothing
+ *    throws across the interface. Parameter checks run on the host before
+ *    any device work, so they need no GPU.
+ *  - A context is not thread-safe; use one context per stream.
+ */
+#ifndef LBHIP_H
+#define LBHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lb_status {
+  LB_OK = 0,
+  LB_E_ARG = -1,            /* invalid parameter or null pointer                      */
+  LB_E_SHAPE = -2,          /* a buffer is smaller than required / size mismatch      */
+  LB_E_OVERLAP = -3,        /* spheres overlap each other or a wall                   */
+  LB_E_CAPACITY = -4,       /* more spheres than params.max_particles                 */
+  LB_E_NONFINITE = -5,      /* a NaN or Inf appeared in the fluid                     */
+  LB_E_PARTICLE_SPEED = -6, /* a sphere moved more than half a node in one step; the
+                               state after that step is not meaningful               */
+  LB_E_HIP = -7,            /* a HIP runtime call failed                              */
+  LB_E_STATE = -8           /* call not valid in the current state                    */
+} lb_status;
+
+typedef enum lb_precision {
+  LB_FP32 = 0, /* populations and fields in FP32 (deviations from w_i rho0_k)          */
+  LB_FP64 = 1  /* populations and fields in FP64 (deviations from w_i rho0_k)          */
+} lb_precision;
+
+typedef struct lb_params {
+  int32_t nx, ny, nz;       /* box; x and y are always periodic                       */
+  int32_t walls;            /* 0: z periodic; 1: solid wall layers z = 0, z = nz-1    */
+  double  wall_u_lo[3];     /* velocity of the z = 0 wall (Eq. bbv)                   */
+  double  wall_u_hi[3];     /* velocity of the z = nz-1 wall                          */
+  int32_t ncomp;            /* 1 or 2 fluid components                                */
+  double  tau[2];           /* BGK relaxation times (> 1/2), Eq. viscosity            */
+  double  G;                /* Shan-Chen coupling G_C, Eq. shanchen                   */
+  double  sc_norm;          /* normalisation s of the Shan-Chen stencil:
+                               F_k = -G s rho_k sum_i w_i psi_kbar(n + c_i) c_i.
+                               s = 1 is the printed equation (repulsive sign)        */
+  double  g[3];             /* body acceleration, force density rho_k g               */
+  double  rho0[2];          /* deviation reference per component (e.g. 1.0)          */
+  int32_t precision;        /* lb_precision                                           */
+  int32_t max_particles;    /* capacity for spheres (0 = none), at most 65534         */
+  double  radius;           /* sphere radius R (< min box size / 2)                   */
+  double  particle_density; /* sphere mass m = density * 4/3 pi R^3, I = 2/5 m R^2    */
+  double  hertz_K;          /* Hertz constant K, Eq. hertzpot                         */
+  double  hertz_d0;         /* contact onset distance (e.g. 2R + 1)                   */
+  double  hertz_rcap;       /* distance below which the contact force is capped      */
+  double  zeta[2];          /* wetting constants zeta_ads, Eq. soliddens              */
+  double  rho_fallback[2];  /* density of a created node that has no fluid neighbour  */
+  int32_t rotate;           /* integrate the rotational motion (Eq. lf3, lf4)         */
+  int32_t particles_fixed;  /* spheres are static obstacles (no map updates, no pair
+                               forces, no integration); needed by lb_backward         */
+  int32_t checkpoint_every; /* > 0: lb_step records a checkpoint every that many
+                               steps so that lb_backward can run (see there)         */
+  int32_t max_record_steps; /* number of steps lb_step may record (with checkpoints) */
+} lb_params;
+
+/* Byte sizes of the caller-owned device buffers. */
+typedef struct lb_sizes {
+  size_t f;          /* one population buffer; two are needed (ping-pong)           */
+  size_t rho;        /* pseudo-potential field psi_k(n), [ncomp][N]                 */
+  size_t owner;      /* one owner map (uint16 per node); two are needed             */
+  size_t particles;  /* FP64 particle state                                         */
+  size_t work;       /* scratch: cell lists, reduction partials, staging, flags     */
+  size_t adjoint;    /* checkpoints and adjoint fields (0 if checkpoint_every == 0) */
+} lb_sizes;
+
+/* Caller-owned device buffers and their allocated byte sizes. */
+typedef struct lb_buffers {
+  void*  f[2];
+  void*  rho;
+  void*  owner[2];
+  void*  particles;
+  void*  work;
+  void*  adjoint;
+  lb_sizes bytes;    /* allocated sizes; each must be >= lb_required_sizes()        */
+} lb_buffers;
+
+/* Observables of the current state (FP64), Sec. 3 statistics / App. C keys. */
+typedef struct lb_obs {
+  int64_t step;          /* steps taken since lb_init                                 */
+  int64_t fluid_nodes;   /* fluid nodes of the current map                            */
+  double  mass[2];       /* sum over fluid nodes of rho_k                              */
+  double  momentum[3];   /* sum over fluid nodes and components of sum_i f_i c_i      */
+  double  rho_min[2], rho_max[2];
+  double  u_max;         /* max over fluid nodes of |u| (mixture velocity, Eq. scvel)  */
+  double  particle_momentum[3];
+  double  particle_ke;   /* sum 1/2 m v^2                                              */
+  double  particle_ke_rot; /* sum 1/2 I w^2                                            */
+  int32_t nparticles;
+  int32_t flags;         /* bit 0: particle speed exceeded, bit 1: non-finite fluid    */
+} lb_obs;
+
+/* Per-sphere record of lb_get_particles / lb_set_particles, FP64, in this order. */
+#define LB_PREC 50
+enum {
+  LB_P_X = 0,        /* position x(t) [3]                                     */
+  LB_P_V = 3,        /* velocity v(t - 1/2) [3]                               */
+  LB_P_W = 6,        /* angular velocity w(t - 1/2), space frame [3]           */
+  LB_P_Q = 9,        /* orientation quaternion q(t) [4]                        */
+  LB_P_FPREV = 13,   /* fluid force F_liq(t - 1/2) [3]                         */
+  LB_P_TPREV = 16,   /* fluid torque T_liq(t - 1/2) [3]                        */
+  /* force terms of the last completed step: */
+  LB_P_FD = 19, LB_P_TD = 22,   /* destroyed nodes (Eq. distr)                 */
+  LB_P_FC = 25, LB_P_TC = 28,   /* created nodes (Eq. creat)                   */
+  LB_P_FH = 31,                 /* Hertz contacts (Eq. hertzpot)               */
+  LB_P_FSC = 34, LB_P_TSC = 37, /* Shan-Chen on frontier solids (Eq. shanchen2) */
+  LB_P_FLIQ = 40, LB_P_TLIQ = 43, /* link momentum exchange (Eq. FORCEPARTEQ,
+                                     TORQUEPARTEQ)                             */
+  LB_P_FLABS = 46,   /* sum over links of |F_link|                             */
+  LB_P_MASS = 47, LB_P_INERTIA = 48,
+  LB_P_HAVEPREV = 49 /* 1 when FPREV/TPREV hold a previous half-step value     */
+};
+
+const char* lb_version(void);
+const char* lb_strerror(int status);
+/* Last error message of a context (or of the last failed lb_init when ctx is NULL). */
+const char* lb_last_error(const struct lb_ctx* ctx);
+
+/* D3Q19 velocities c [19][3] and weights w [19] in the library's order
+ * (Sec. 2.1). Host only. */
+int lb_lattice(int32_t* c, double* w);
+
+/* Device buffer sizes for params. Host only; validates params.
+ * Errors: LB_E_ARG (null or invalid parameters), LB_E_SHAPE (box too large). */
+int lb_required_sizes(const lb_params* params, lb_sizes* out);
+
+/* Create a context on the caller's buffers and stream (hipStream_t, NULL =
+ * default stream) and set f^k_i = f_eq(rho0_k(n), u0(n)) (Eq. LEQ).
+ * rho0: host FP64 [ncomp][N]; u0: host FP64 [N][3] or NULL for rest.
+ * Synchronises. Errors: LB_E_ARG, LB_E_SHAPE, LB_E_HIP. */
+int lb_init(const lb_params* params, const lb_buffers* buffers, const double* rho0,
+            const double* u0, void* hip_stream, struct lb_ctx** out);
+
+/* Add n spheres of the common radius (Sec. 2.4): host FP64 centres x [n][3],
+ * velocities v [n][3] (NULL = 0), angular velocities w [n][3] (NULL = 0),
+ * quaternions q [n][4] (NULL = identity). Nodes inside a sphere become solid
+ * and their populations are discarded. Allowed before the first step only.
+ * Synchronises. Errors: LB_E_CAPACITY, LB_E_OVERLAP (centres closer than
+ * 2R, or a sphere reaching a wall layer), LB_E_STATE, LB_E_HIP. */
+int lb_add_particles(struct lb_ctx* ctx, int32_t n, const double* x, const double* v,
+                     const double* w, const double* q);
+
+/* Advance nsteps time steps (Sec. 3.1, eight-step sequence). Asynchronous on
+ * the context's stream. A sphere faster than 1/2 node per step is flagged
+ * and reported by the next synchronising call. With checkpoint_every > 0 the
+ * steps are recorded for lb_backward (LB_E_CAPACITY beyond max_record_steps).
+ * Errors: LB_E_ARG, LB_E_HIP, LB_E_CAPACITY. */
+int lb_step(struct lb_ctx* ctx, int32_t nsteps);
+
+/* FP64 observables of the current state. Synchronises.
+ * Errors: LB_E_PARTICLE_SPEED / LB_E_NONFINITE when flagged (out is still filled). */
+int lb_observables(struct lb_ctx* ctx, lb_obs* out);
+
+/* Moments of the current state on fluid nodes (0 on solid nodes), host FP64:
+ * rho [ncomp][N] and mixture velocity u [N][3] (Eq. scvel; NULL to skip). Synchronises. */
+int lb_get_fields(struct lb_ctx* ctx, double* rho, double* u);
+
+/* Pseudo-potential psi_k(n) of the last step (fluid densities plus virtual
+ * densities of frontier solids, Eq. soliddens), host FP64 [ncomp][N]. Synchronises. */
+int lb_get_psi(struct lb_ctx* ctx, double* psi);
+
+/* Post-streaming populations f^k_i(n, t), host FP64 [ncomp][19][N] (full
+ * values, direction order of lb_lattice, 0 on solid nodes). Synchronises. */
+int lb_get_populations(struct lb_ctx* ctx, double* f);
+/* Replace the populations of the fluid nodes of the current map (same layout).
+ * Values are rounded to the storage precision. Synchronises. */
+int lb_set_populations(struct lb_ctx* ctx, const double* f);
+
+/* Owner map of the current state: 0 fluid, p+1 node of sphere p, -1 wall;
+ * host int32 [N]. Synchronises. */
+int lb_get_owner(struct lb_ctx* ctx, int32_t* owner);
+
+/* Sphere records (LB_PREC doubles each), host FP64 [nparticles][LB_PREC].
+ * lb_set_particles writes x, v, w, q, FPREV, TPREV, HAVEPREV of existing
+ * spheres and re-rasterises the map without fluid-node events. Synchronises. */
+int lb_get_particles(struct lb_ctx* ctx, double* rec);
+int lb_set_particles(struct lb_ctx* ctx, const double* rec);
+int lb_num_particles(const struct lb_ctx* ctx);
+
+/* Loss of the differentiation study on the current state:
+ * L = sum over fluid nodes of |grad_lat phi|^2, phi = psi_A - psi_B,
+ * grad_lat phi(n) = 3 sum_i w_i phi(n + c_i) c_i, psi with the virtual
+ * densities of the current map. L to host; optionally dL/dpsi_k(n) into
+ * device FP64 arrays dL_dpsiA, dL_dpsiB [N] (NULL to skip). Synchronises. */
+int lb_loss(struct lb_ctx* ctx, double* L, double* dL_dpsiA, double* dL_dpsiB);
+
+/* Reverse-mode derivative of a loss of the final pseudo-potential through
+ * every recorded step, with checkpoint recomputation. Inputs: device FP64
+ * seeds dL/dpsi_k(n) at the final state [N] each (dL_dpsiB may be NULL).
+ * Outputs: device FP64 dL/drho0_A(n) [N] of the initial density of component
+ * A (the state set by lb_init with u0 = 0), and host dL/dG and dL/dg[3].
+ * Requires checkpoint_every > 0, equal relaxation times, no moving spheres
+ * (particles_fixed or none) and zero wall velocities. Synchronises.
+ * Errors: LB_E_STATE, LB_E_ARG, LB_E_HIP. */
+int lb_backward(struct lb_ctx* ctx, const double* dL_dpsiA, const double* dL_dpsiB,
+                double* dL_drhoA0, double* dL_dG, double dL_dg[3]);
+
+/* Wait for all work queued by the context. */
+int lb_sync(struct lb_ctx* ctx);
+
+/* Per-phase GPU timing with HIP events recorded on the context's stream around
+ * the kernels of each phase of lb_step. lb_timing(ctx, 1) clears the totals
+ * and starts recording, lb_timing(ctx, 0) stops. lb_timing_read synchronises
+ * and returns the summed milliseconds and launch counts per phase:
+ * 0 moments (density), 1 sphere map/events/pairs, 2 virtual-density fills,
+ * 3 collide-stream-bounce-back, 4 sphere integration. */
+#define LB_NPHASE 5
+int lb_timing(struct lb_ctx* ctx, int enable);
+int lb_timing_read(struct lb_ctx* ctx, double ms[LB_NPHASE], int64_t count[LB_NPHASE]);
+
+/* Destroy a context (does not free the caller's buffers). NULL is ignored. */
+void lb_free(struct lb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

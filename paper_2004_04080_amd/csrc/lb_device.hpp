@@ -1,0 +1,88 @@
+// lb_device.hpp -- lattice constants and device helpers of the gfx950 path.
+//
+// D3Q19 (Sec. 2.1 of the LBsoft paper): weights 1/3, 1/18, 1/36, c_s^2 = 1/3.
+// The library's direction order groups the velocities by c_z so that the
+// pull-gather of a z-plane reads the planes z+1, z and z-1 in three blocks:
+//   0            rest
+//   1..8         c_z =  0: +x -x +y -y (+x+y) (-x-y) (+x-y) (-x+y)
+//   9..13        c_z = +1: (0,0) (+x) (-x) (+y) (-y)
+//   14..18       c_z = -1: (0,0) (-x) (+x) (-y) (+y)
+// so that opp(i) = i+5 for 9..13 and i-5 for 14..18.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbh {
+
+constexpr int Q = 19;
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 1, -1, 0, 0, 0, -1, 1, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 1, -1, -1, 1, 0, 0, 0, 1, -1, 0, 0, 0, -1, 1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, -1, -1, -1, -1, -1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 14, 15, 16, 17, 18, 9, 10, 11, 12, 13};
+constexpr double W1 = 1.0 / 18.0, W2 = 1.0 / 36.0;
+constexpr double WQ[Q] = {1.0 / 3.0, W1, W1, W1, W1, W2, W2, W2, W2, W1,
+                          W2, W2, W2, W2, W1, W2, W2, W2, W2};
+
+constexpr uint16_t OWN_WALL = 0xFFFF;   // owner value of a wall node
+constexpr int PSTRIDE = 32;             // doubles per sphere in the state array
+constexpr int ASTRIDE = 32;             // doubles per sphere in the accumulator array
+
+// sphere state record (AoS, PSTRIDE doubles)
+enum : int {
+  PS_X = 0, PS_V = 3, PS_W = 6, PS_Q = 9, PS_FPREV = 13, PS_TPREV = 16,
+  PS_XRA = 19,   // centre used for the map of the previous step M_{t-1}
+  PS_XRB = 22,   // centre used for the map two steps back (ping-pong partner)
+  PS_HAVEPREV = 25
+};
+// per-step accumulators (AoS, ASTRIDE doubles)
+enum : int {
+  AC_FLIQ = 0, AC_TLIQ = 3, AC_FLABS = 6, AC_FD = 8, AC_TD = 11, AC_FC = 14, AC_TC = 17,
+  AC_FSC = 20, AC_TSC = 23, AC_FH = 26
+};
+
+// Periodic neighbour addressing of node (x, y, z): index of (x+dx, y+dy, z+dz)
+// for dx, dy, dz in {-1, 0, 1}.
+struct Nbr {
+  uint32_t xs[3];
+  uint32_t rows[3][3];  // [dy+1][dz+1] -> nx * (y' + ny * z')
+  __device__ __forceinline__ Nbr(uint32_t x, uint32_t y, uint32_t z, uint32_t nx, uint32_t ny,
+                                 uint32_t nz) {
+    xs[0] = x == 0 ? nx - 1 : x - 1;
+    xs[1] = x;
+    xs[2] = x + 1 == nx ? 0 : x + 1;
+    uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y + 1 == ny ? 0 : y + 1};
+    uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z + 1 == nz ? 0 : z + 1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) rows[a][b] = nx * (ys[a] + ny * zs[b]);
+  }
+  // node n + c_i
+  __device__ __forceinline__ uint32_t push(int i) const {
+    return xs[CX[i] + 1] + rows[CY[i] + 1][CZ[i] + 1];
+  }
+  // node n - c_i
+  __device__ __forceinline__ uint32_t pull(int i) const {
+    return xs[1 - CX[i]] + rows[1 - CY[i]][1 - CZ[i]];
+  }
+};
+
+__device__ __forceinline__ void node_xyz(uint32_t n, uint32_t nx, uint32_t ny, uint32_t& x,
+                                         uint32_t& y, uint32_t& z) {
+  x = n % nx;
+  uint32_t t = n / nx;
+  y = t % ny;
+  z = t / ny;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) {
+  return d - L * rint(d / L);
+}
+
+__device__ __forceinline__ int wrap_int(int v, int L) {
+  v %= L;
+  return v < 0 ? v + L : v;
+}
+
+}  // namespace lbh

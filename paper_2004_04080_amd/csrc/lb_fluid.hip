@@ -1,0 +1,743 @@
+// lb_fluid.hip -- fluid kernels of the gfx950 path.
+//
+// Storage: two population buffers f[k][i][n] (SoA, x fastest) holding the
+// post-collision populations of the previous step in pull form: the value
+// that streams into node n along c_i sits at slot (i, n - c_i). Solid nodes'
+// slots carry the reflected values of the links that end on them, so the
+// pull-gather needs no bounce-back branch. Values are deviations
+// f_i - w_i rho0_k in the storage type `real` (float or double).
+#include <hip/hip_runtime.h>
+
+#include "lb_device.hpp"
+#include "lb_internal.hpp"
+
+namespace lbh {
+
+constexpr int BLOCK = 256;
+
+static inline uint32_t nblocks(uint64_t n) { return uint32_t((n + BLOCK - 1) / BLOCK); }
+
+// ---------------------------------------------------------------------------
+// Initial populations f_i = f_eq(rho0(n), u0(n)) (Eq. LEQ), written in pull form.
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(BLOCK)
+k_init(real* __restrict__ f, const double* __restrict__ rho0, const double* __restrict__ u0,
+       const uint16_t* __restrict__ owner, uint32_t first, uint32_t count, uint32_t nx,
+       uint32_t ny, uint32_t nz, int ncomp, double r0a, double r0b) {
+  const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= count) return;
+  const uint32_t n = first + t, N = nx * ny * nz;
+  if (owner && owner[n] != 0) return;
+  uint32_t x, y, z;
+  node_xyz(n, nx, ny, x, y, z);
+  Nbr nb(x, y, z, nx, ny, nz);
+  double ux = 0, uy = 0, uz = 0;
+  if (u0) {
+    ux = u0[3 * size_t(t)];
+    uy = u0[3 * size_t(t) + 1];
+    uz = u0[3 * size_t(t) + 2];
+  }
+  const double uu = ux * ux + uy * uy + uz * uz;
+  for (int k = 0; k < ncomp; ++k) {
+    const double r = rho0[size_t(k) * count + t];
+    const double ref = k == 0 ? r0a : r0b;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+      const double dev = WQ[i] * (r - ref) + WQ[i] * r * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+      f[(size_t(k) * Q + i) * N + nb.pull(i)] = real(dev);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Moments of the pull-gathered populations: psi_k(n) - rho0_k = sum_i df_i.
+// Written for every node; solid nodes get overwritten by the fill kernels.
+// ---------------------------------------------------------------------------
+template <typename real, int NC>
+__global__ void __launch_bounds__(BLOCK)
+k_density(const real* __restrict__ f, real* __restrict__ psi, uint32_t nx, uint32_t ny,
+          uint32_t nz) {
+  const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t N = nx * ny * nz;
+  if (n >= N) return;
+  uint32_t x, y, z;
+  node_xyz(n, nx, ny, x, y, z);
+  Nbr nb(x, y, z, nx, ny, nz);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const real* fk = f + size_t(k) * Q * N;
+    real s = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s += fk[size_t(i) * N + nb.pull(i)];
+    psi[size_t(k) * N + n] = s;
+  }
+}
+
+struct CollideArgs {
+  const void* fin;
+  void* fout;
+  const void* psi;
+  const uint16_t* owner;
+  const double* ps;   // sphere state records
+  double* acc;        // sphere accumulators
+  uint32_t nx, ny, nz, N;
+  double Gs;          // G * sc_norm
+  double g[3];
+  double rho0[2];
+  double inv_tau[2];
+  double nu[2];       // c_s^2 (tau_k - 1/2)
+  double omega;       // relaxation rate when the relaxation times are equal
+  int equal_tau;
+  double wall_lo[3], wall_hi[3];
+  double L[3];
+};
+
+// Wave-level segmented reduction of per-lane link force/torque contributions
+// keyed by sphere id, then one FP64 atomic per (wave, sphere, component).
+// Every lane of the wave must call this (inactive contributions use pid < 0).
+__device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, double v[7]) {
+  const int lane = __lane_id();
+  uint64_t pending = __ballot(pid >= 0);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int lp = __shfl(pid, leader);
+    const bool mine = pid == lp;
+    double s[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s[c] = mine ? v[c] : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) s[c] += __shfl_xor(s[c], off);
+    if (lane == leader) {
+      double* a = acc + size_t(lp) * ASTRIDE;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) unsafeAtomicAdd(a + AC_FLIQ + c, s[c]);
+      unsafeAtomicAdd(a + AC_FLABS, s[6]);
+    }
+    if (mine) pid = -1;
+    pending = __ballot(pid >= 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fused step for one fluid node: pull-gather (Eq. bgk2), moments and
+// mixture velocity (Eq. rho, vel, scvel), Shan-Chen acceleration from the
+// pseudo-potential of the neighbours (Eq. shanchen), EDM collision
+// (Eq. lbsbgk), store; then for every link ending on a solid node the
+// moving-wall reflection (Eq. LADDFLBE, UPI) into that node's slot and the
+// link momentum exchange (Eq. LADDFORCE) reduced per sphere.
+// In deviation form with E_i(v) = w_i rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v):
+//   df*_i = w_i drho + E_i(u + a) + (1 - omega)(df_i - w_i drho - E_i(u)).
+// ---------------------------------------------------------------------------
+template <typename real, int NC, bool SOLIDS>
+__global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
+  const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t N = a.N;
+  bool fluid = n < N;
+  if (SOLIDS && fluid) fluid = a.owner[n] == 0;
+  int pid = -1;
+  double lv[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (fluid) {
+    uint32_t x, y, z;
+    node_xyz(n, a.nx, a.ny, x, y, z);
+    Nbr nb(x, y, z, a.nx, a.ny, a.nz);
+    const real* __restrict__ fin = static_cast<const real*>(a.fin);
+    real* __restrict__ fout = static_cast<real*>(a.fout);
+    const real* __restrict__ psi = static_cast<const real*>(a.psi);
+
+    real f[NC][Q];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[k][i] = fin[(size_t(k) * Q + i) * N + nb.pull(i)];
+
+    real drho[NC], rho[NC], jx[NC], jy[NC], jz[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      // momentum from differences of opposite populations: f_i and f_opp(i)
+      // are close, so the differences (and their sums) carry few rounding errors
+      real s = f[k][0], sx = 0, sy = 0, sz = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        s += f[k][i];
+        if (OPP[i] < i) continue;
+        const real d = f[k][i] - f[k][OPP[i]];
+        if (CX[i]) sx += CX[i] > 0 ? d : -d;
+        if (CY[i]) sy += CY[i] > 0 ? d : -d;
+        if (CZ[i]) sz += CZ[i] > 0 ? d : -d;
+      }
+      drho[k] = s;
+      rho[k] = real(a.rho0[k]) + s;
+      jx[k] = sx;
+      jy[k] = sy;
+      jz[k] = sz;
+    }
+    real ux, uy, uz;
+    if (NC == 1) {
+      const real ir = real(1) / rho[0];
+      ux = jx[0] * ir;
+      uy = jy[0] * ir;
+      uz = jz[0] * ir;
+    } else {
+      const real t0 = real(a.inv_tau[0]), t1 = real(a.inv_tau[NC - 1]);
+      const real id = real(1) / (rho[0] * t0 + rho[NC - 1] * t1);
+      ux = (jx[0] * t0 + jx[NC - 1] * t1) * id;
+      uy = (jy[0] * t0 + jy[NC - 1] * t1) * id;
+      uz = (jz[0] * t0 + jz[NC - 1] * t1) * id;
+    }
+    real ax[NC], ay[NC], az[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      ax[k] = real(a.g[0]);
+      ay[k] = real(a.g[1]);
+      az[k] = real(a.g[2]);
+    }
+    if (NC == 2) {
+      // sum_i w_i psi(n + c_i) c_i; the rho0 part cancels because every
+      // neighbour of a fluid node is fluid or a frontier solid with psi.
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const real* pk = psi + size_t(NC - 1 - k) * N;
+        real sx = 0, sy = 0, sz = 0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          if (OPP[i] < i) continue;
+          // w_i (psi(n + c_i) - psi(n - c_i)) c_i over pairs of opposite directions
+          const real p = (pk[nb.push(i)] - pk[nb.pull(i)]) * real(WQ[i]);
+          if (CX[i]) sx += CX[i] > 0 ? p : -p;
+          if (CY[i]) sy += CY[i] > 0 ? p : -p;
+          if (CZ[i]) sz += CZ[i] > 0 ? p : -p;
+        }
+        const real gs = real(a.Gs);
+        ax[k] -= gs * sx;
+        ay[k] -= gs * sy;
+        az[k] -= gs * sz;
+      }
+    }
+    real om;
+    if (NC == 1 || a.equal_tau) {
+      om = real(a.omega);
+    } else {
+      // mixture viscosity 1/nu_bar = sum_k (rho_k/rho)/nu_k; omega = 2 cs2/(2 nu_bar + cs2)
+      const real rt = rho[0] + rho[NC - 1];
+      const real inv_nu = (rho[0] / real(a.nu[0]) + rho[NC - 1] / real(a.nu[NC - 1])) / rt;
+      const real nub = real(1) / inv_nu;
+      om = real(2.0 / 3.0) / (real(2) * nub + real(1.0 / 3.0));
+    }
+    const real omc = real(1) - om;
+    const real uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const real vx = ux + ax[k], vy = uy + ay[k], vz = uz + az[k];
+      const real vv = vx * vx + vy * vy + vz * vz;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const real w = real(WQ[i]);
+        const real cu = real(CX[i]) * ux + real(CY[i]) * uy + real(CZ[i]) * uz;
+        const real cv = real(CX[i]) * vx + real(CY[i]) * vy + real(CZ[i]) * vz;
+        const real wr = w * rho[k];
+        const real eu = wr * (real(3) * cu + real(4.5) * cu * cu - real(1.5) * uu);
+        const real ev = wr * (real(3) * cv + real(4.5) * cv * cv - real(1.5) * vv);
+        const real wd = w * drho[k];
+        const real fs = wd + ev + omc * (f[k][i] - wd - eu);
+        f[k][i] = fs;
+        fout[(size_t(k) * Q + i) * N + n] = fs;
+      }
+    }
+    if (SOLIDS) {
+      const double rho0sum = a.rho0[0] + (NC == 2 ? a.rho0[1] : 0.0);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const uint32_t s = nb.push(i);
+        const uint16_t o = a.owner[s];
+        if (o == 0) continue;
+        double uwx, uwy, uwz, rwx = 0, rwy = 0, rwz = 0;
+        int p = -1;
+        if (o == OWN_WALL) {
+          const double* U = (int(z) + CZ[i] == 0) ? a.wall_lo : a.wall_hi;
+          uwx = U[0];
+          uwy = U[1];
+          uwz = U[2];
+        } else {
+          p = int(o) - 1;
+          const double* P = a.ps + size_t(p) * PSTRIDE;
+          rwx = min_image(double(x) + 0.5 * CX[i] - P[PS_X], a.L[0]);
+          rwy = min_image(double(y) + 0.5 * CY[i] - P[PS_X + 1], a.L[1]);
+          rwz = min_image(double(z) + 0.5 * CZ[i] - P[PS_X + 2], a.L[2]);
+          const double wx = P[PS_W], wy = P[PS_W + 1], wz = P[PS_W + 2];
+          uwx = P[PS_V] + (wy * rwz - wz * rwy);
+          uwy = P[PS_V + 1] + (wz * rwx - wx * rwz);
+          uwz = P[PS_V + 2] + (wx * rwy - wy * rwx);
+        }
+        const double cuw = uwx * CX[i] + uwy * CY[i] + uwz * CZ[i];
+        const real cw = real(6.0 * WQ[i] * cuw);
+        double dev = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          const real corr = cw * rho[k];
+          fout[(size_t(k) * Q + OPP[i]) * N + s] = f[k][i] - corr;
+          dev += double(real(2) * f[k][i] - corr);
+        }
+        if (p >= 0) {
+          const double fl = 2.0 * WQ[i] * rho0sum + dev;  // F_link = fl * c_i
+          const double Fx = fl * CX[i], Fy = fl * CY[i], Fz = fl * CZ[i];
+          if (p != pid) {
+            if (pid >= 0) {  // a node touching two spheres: flush the first one
+              double* acp = a.acc + size_t(pid) * ASTRIDE;
+              for (int c = 0; c < 6; ++c) unsafeAtomicAdd(acp + AC_FLIQ + c, lv[c]);
+              unsafeAtomicAdd(acp + AC_FLABS, lv[6]);
+            }
+            pid = p;
+            for (int c = 0; c < 7; ++c) lv[c] = 0.0;
+          }
+          lv[0] += Fx;
+          lv[1] += Fy;
+          lv[2] += Fz;
+          lv[3] += rwy * Fz - rwz * Fy;
+          lv[4] += rwz * Fx - rwx * Fz;
+          lv[5] += rwx * Fy - rwy * Fx;
+          lv[6] += fabs(fl) * ((CX[i] && CY[i]) || (CX[i] && CZ[i]) || (CY[i] && CZ[i])
+                                   ? 1.4142135623730951
+                                   : 1.0);
+        }
+      }
+    }
+  }
+  if (SOLIDS && a.acc) flush_links(a.acc, pid, lv);
+}
+
+// ---------------------------------------------------------------------------
+// Virtual densities of wall frontier nodes (Eq. soliddens): the two wall
+// layers take the w-weighted mean of their fluid neighbours.
+// ---------------------------------------------------------------------------
+template <typename real, int NC>
+__global__ void __launch_bounds__(BLOCK)
+k_fill_walls(real* __restrict__ psi, const uint16_t* __restrict__ owner, uint32_t nx,
+             uint32_t ny, uint32_t nz, double z0a, double z0b, double r0a, double r0b) {
+  const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t plane = nx * ny;
+  if (t >= 2 * plane) return;
+  const uint32_t x = t % nx, y = (t / nx) % ny, z = t < plane ? 0 : nz - 1;
+  const uint32_t N = plane * nz;
+  const uint32_t n = x + nx * (y + ny * z);
+  Nbr nb(x, y, z, nx, ny, nz);
+  double wsum = 0, s[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) s[k] = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const uint32_t m = nb.push(i);
+    if (owner[m] != 0) continue;
+    wsum += WQ[i];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) s[k] += WQ[i] * double(psi[size_t(k) * N + m]);
+  }
+  if (wsum == 0.0) return;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const double zeta = k == 0 ? z0a : z0b, ref = k == 0 ? r0a : r0b;
+    psi[size_t(k) * N + n] = real(zeta * ref + (1.0 + zeta) * s[k] / wsum);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// State transfer: post-streaming populations of the fluid nodes (full values).
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(BLOCK)
+k_get_pop(const real* __restrict__ fki, const uint16_t* __restrict__ owner, uint32_t first,
+          uint32_t count, uint32_t nx, uint32_t ny, uint32_t nz, int i, double ref,
+          double* __restrict__ out) {
+  const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= count) return;
+  const uint32_t n = first + t;
+  if (owner && owner[n] != 0) {
+    out[t] = 0.0;
+    return;
+  }
+  uint32_t x, y, z;
+  node_xyz(n, nx, ny, x, y, z);
+  Nbr nb(x, y, z, nx, ny, nz);
+  out[t] = WQ[i] * ref + double(fki[nb.pull(i)]);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(BLOCK)
+k_set_pop(real* __restrict__ fki, const uint16_t* __restrict__ owner, uint32_t first,
+          uint32_t count, uint32_t nx, uint32_t ny, uint32_t nz, int i, double ref,
+          const double* __restrict__ in) {
+  const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= count) return;
+  const uint32_t n = first + t;
+  if (owner && owner[n] != 0) return;
+  uint32_t x, y, z;
+  node_xyz(n, nx, ny, x, y, z);
+  Nbr nb(x, y, z, nx, ny, nz);
+  fki[nb.pull(i)] = real(in[t] - WQ[i] * ref);
+}
+
+// Moments of a chunk of nodes: out [ncomp + 3][count] = rho_k, u (0 on solids).
+template <typename real>
+__global__ void __launch_bounds__(BLOCK)
+k_get_fields(const real* __restrict__ f, const uint16_t* __restrict__ owner, uint32_t first,
+             uint32_t count, uint32_t nx, uint32_t ny, uint32_t nz, int ncomp, double r0a,
+             double r0b, double it0, double it1, double* __restrict__ out) {
+  const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= count) return;
+  const uint32_t n = first + t, N = nx * ny * nz;
+  double rho[2] = {0, 0}, j[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  double u[3] = {0, 0, 0};
+  if (!owner || owner[n] == 0) {
+    uint32_t x, y, z;
+    node_xyz(n, nx, ny, x, y, z);
+    Nbr nb(x, y, z, nx, ny, nz);
+    double num[3] = {0, 0, 0}, den = 0;
+    for (int k = 0; k < ncomp; ++k) {
+      double s = 0;
+      for (int i = 0; i < Q; ++i) {
+        const double v = double(f[(size_t(k) * Q + i) * N + nb.pull(i)]);
+        s += v;
+        j[k][0] += v * CX[i];
+        j[k][1] += v * CY[i];
+        j[k][2] += v * CZ[i];
+      }
+      rho[k] = (k == 0 ? r0a : r0b) + s;
+      const double it = k == 0 ? it0 : it1;
+      for (int c = 0; c < 3; ++c) num[c] += j[k][c] * it;
+      den += rho[k] * it;
+    }
+    for (int c = 0; c < 3; ++c) u[c] = num[c] / den;
+  }
+  for (int k = 0; k < ncomp; ++k) out[size_t(k) * count + t] = rho[k];
+  for (int c = 0; c < 3; ++c) out[size_t(ncomp + c) * count + t] = u[c];
+}
+
+template <typename real>
+__global__ void __launch_bounds__(BLOCK)
+k_get_psi(const real* __restrict__ psi, const uint16_t* __restrict__ owner, uint32_t first,
+          uint32_t count, uint32_t nx, uint32_t ny, uint32_t nz, double ref,
+          double* __restrict__ out) {
+  const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= count) return;
+  const uint32_t n = first + t;
+  bool valid = true;
+  if (owner && owner[n] != 0) {  // solid: valid only on the frontier
+    uint32_t x, y, z;
+    node_xyz(n, nx, ny, x, y, z);
+    Nbr nb(x, y, z, nx, ny, nz);
+    valid = false;
+    for (int i = 1; i < Q; ++i) valid = valid || owner[nb.push(i)] == 0;
+  }
+  out[t] = valid ? ref + double(psi[n]) : 0.0;
+}
+
+__global__ void k_owner_to_int(const uint16_t* __restrict__ owner, uint32_t first,
+                               uint32_t count, int32_t* __restrict__ out) {
+  const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= count) return;
+  const uint16_t o = owner ? owner[first + t] : 0;
+  out[t] = o == OWN_WALL ? -1 : int32_t(o);
+}
+
+// ---------------------------------------------------------------------------
+// Observables: deterministic two-level FP64 reduction over the fluid nodes.
+// partial[b][*]: 0,1 sum drho_k; 2..4 momentum; 5,6 min drho_k; 7,8 max drho_k;
+// 9 max |u|; 10 fluid nodes; 11 non-finite count.
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(BLOCK)
+k_reduce_partials(const real* __restrict__ f, const uint16_t* __restrict__ owner, uint32_t nx,
+                  uint32_t ny, uint32_t nz, int ncomp, double r0a, double r0b, double it0,
+                  double it1, double* __restrict__ partial) {
+  const uint32_t N = nx * ny * nz;
+  double v[RED_N];
+  for (int c = 0; c < RED_N; ++c) v[c] = 0.0;
+  v[5] = v[6] = 1e300;
+  v[7] = v[8] = -1e300;
+  for (uint32_t n = blockIdx.x * BLOCK + threadIdx.x; n < N; n += gridDim.x * BLOCK) {
+    if (owner && owner[n] != 0) continue;
+    uint32_t x, y, z;
+    node_xyz(n, nx, ny, x, y, z);
+    Nbr nb(x, y, z, nx, ny, nz);
+    double num[3] = {0, 0, 0}, den = 0;
+    for (int k = 0; k < ncomp; ++k) {
+      double s = 0, j[3] = {0, 0, 0};
+      for (int i = 0; i < Q; ++i) {
+        const double d = double(f[(size_t(k) * Q + i) * N + nb.pull(i)]);
+        s += d;
+        j[0] += d * CX[i];
+        j[1] += d * CY[i];
+        j[2] += d * CZ[i];
+      }
+      v[k] += s;
+      for (int c = 0; c < 3; ++c) v[2 + c] += j[c];
+      v[5 + k] = fmin(v[5 + k], s);
+      v[7 + k] = fmax(v[7 + k], s);
+      if (!isfinite(s)) v[11] += 1.0;
+      const double it = k == 0 ? it0 : it1;
+      for (int c = 0; c < 3; ++c) num[c] += j[c] * it;
+      den += ((k == 0 ? r0a : r0b) + s) * it;
+    }
+    const double ux = num[0] / den, uy = num[1] / den, uz = num[2] / den;
+    v[9] = fmax(v[9], sqrt(ux * ux + uy * uy + uz * uz));
+    v[10] += 1.0;
+  }
+  __shared__ double sh[BLOCK];
+  for (int c = 0; c < 12; ++c) {
+    sh[threadIdx.x] = v[c];
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        const double o = sh[threadIdx.x + s];
+        double& m = sh[threadIdx.x];
+        if (c == 5 || c == 6) m = fmin(m, o);
+        else if (c == 7 || c == 8 || c == 9) m = fmax(m, o);
+        else m += o;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[size_t(blockIdx.x) * RED_N + c] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* __restrict__ partial,
+                                                        int nb, double* __restrict__ out) {
+  __shared__ double sh[BLOCK];
+  for (int c = 0; c < 12; ++c) {
+    double acc = (c == 5 || c == 6) ? 1e300 : (c == 7 || c == 8 || c == 9) ? -1e300 : 0.0;
+    for (int b = threadIdx.x; b < nb; b += BLOCK) {
+      const double o = partial[size_t(b) * RED_N + c];
+      if (c == 5 || c == 6) acc = fmin(acc, o);
+      else if (c == 7 || c == 8 || c == 9) acc = fmax(acc, o);
+      else acc += o;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        const double o = sh[threadIdx.x + s];
+        double& m = sh[threadIdx.x];
+        if (c == 5 || c == 6) m = fmin(m, o);
+        else if (c == 7 || c == 8 || c == 9) m = fmax(m, o);
+        else m += o;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sh[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline bool fp64(const lb_ctx* c) { return c->geo.prec == LB_FP64; }
+
+hipError_t launch_init_populations(lb_ctx* c, const double* rho0, const double* u0,
+                                   uint32_t first, uint32_t count) {
+  const auto& g = c->geo;
+  const uint16_t* own = c->has_solids ? static_cast<const uint16_t*>(c->B.owner[c->own_old]) : nullptr;
+  if (fp64(c))
+    hipLaunchKernelGGL(k_init<double>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<double*>(c->B.f[c->cur]), rho0, u0, own, first, count,
+                       g.nx, g.ny, g.nz, g.ncomp, c->P.rho0[0], c->P.rho0[1]);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<float*>(c->B.f[c->cur]), rho0, u0, own, first, count,
+                       g.nx, g.ny, g.nz, g.ncomp, c->P.rho0[0], c->P.rho0[1]);
+  return hipGetLastError();
+}
+
+hipError_t launch_density(lb_ctx* c, const void* f) {
+  const auto& g = c->geo;
+  dim3 grid(nblocks(g.N));
+  if (fp64(c)) {
+    if (g.ncomp == 2)
+      hipLaunchKernelGGL((k_density<double, 2>), grid, dim3(BLOCK), 0, c->stream,
+                         static_cast<const double*>(f), static_cast<double*>(c->B.rho), g.nx, g.ny, g.nz);
+    else
+      hipLaunchKernelGGL((k_density<double, 1>), grid, dim3(BLOCK), 0, c->stream,
+                         static_cast<const double*>(f), static_cast<double*>(c->B.rho), g.nx, g.ny, g.nz);
+  } else {
+    if (g.ncomp == 2)
+      hipLaunchKernelGGL((k_density<float, 2>), grid, dim3(BLOCK), 0, c->stream,
+                         static_cast<const float*>(f), static_cast<float*>(c->B.rho), g.nx, g.ny, g.nz);
+    else
+      hipLaunchKernelGGL((k_density<float, 1>), grid, dim3(BLOCK), 0, c->stream,
+                         static_cast<const float*>(f), static_cast<float*>(c->B.rho), g.nx, g.ny, g.nz);
+  }
+  return hipGetLastError();
+}
+
+template <typename real, int NC>
+static void collide_t(lb_ctx* c, const CollideArgs& a) {
+  dim3 grid(nblocks(c->geo.N));
+  if (c->has_solids)
+    hipLaunchKernelGGL((k_collide<real, NC, true>), grid, dim3(BLOCK), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_collide<real, NC, false>), grid, dim3(BLOCK), 0, c->stream, a);
+}
+
+hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t* owner) {
+  const auto& g = c->geo;
+  const auto& P = c->P;
+  CollideArgs a;
+  a.fin = fin;
+  a.fout = fout;
+  a.psi = c->B.rho;
+  a.owner = owner;
+  a.ps = c->nparticles ? pstate(c) : nullptr;
+  a.acc = c->nparticles ? pacc(c) : nullptr;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.N = g.N;
+  a.Gs = P.G * P.sc_norm;
+  for (int d = 0; d < 3; ++d) {
+    a.g[d] = P.g[d];
+    a.wall_lo[d] = P.wall_u_lo[d];
+    a.wall_hi[d] = P.wall_u_hi[d];
+  }
+  a.L[0] = g.nx;
+  a.L[1] = g.ny;
+  a.L[2] = g.nz;
+  const int kb = g.ncomp == 2 ? 1 : 0;
+  a.rho0[0] = P.rho0[0];
+  a.rho0[1] = P.rho0[kb];
+  a.inv_tau[0] = 1.0 / P.tau[0];
+  a.inv_tau[1] = 1.0 / P.tau[kb];
+  a.nu[0] = (P.tau[0] - 0.5) / 3.0;
+  a.nu[1] = (P.tau[kb] - 0.5) / 3.0;
+  a.equal_tau = P.tau[0] == P.tau[kb];
+  a.omega = 1.0 / P.tau[0];
+  if (fp64(c)) {
+    if (g.ncomp == 2) collide_t<double, 2>(c, a);
+    else collide_t<double, 1>(c, a);
+  } else {
+    if (g.ncomp == 2) collide_t<float, 2>(c, a);
+    else collide_t<float, 1>(c, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_walls(lb_ctx* c, const uint16_t* owner) {
+  const auto& g = c->geo;
+  const auto& P = c->P;
+  dim3 grid(nblocks(2ull * g.nx * g.ny));
+  const double z1 = g.ncomp == 2 ? P.zeta[1] : 0.0, r1 = g.ncomp == 2 ? P.rho0[1] : 0.0;
+  if (fp64(c)) {
+    if (g.ncomp == 2)
+      hipLaunchKernelGGL((k_fill_walls<double, 2>), grid, dim3(BLOCK), 0, c->stream,
+                         static_cast<double*>(c->B.rho), owner, g.nx, g.ny, g.nz, P.zeta[0], z1, P.rho0[0], r1);
+    else
+      hipLaunchKernelGGL((k_fill_walls<double, 1>), grid, dim3(BLOCK), 0, c->stream,
+                         static_cast<double*>(c->B.rho), owner, g.nx, g.ny, g.nz, P.zeta[0], z1, P.rho0[0], r1);
+  } else {
+    if (g.ncomp == 2)
+      hipLaunchKernelGGL((k_fill_walls<float, 2>), grid, dim3(BLOCK), 0, c->stream,
+                         static_cast<float*>(c->B.rho), owner, g.nx, g.ny, g.nz, P.zeta[0], z1, P.rho0[0], r1);
+    else
+      hipLaunchKernelGGL((k_fill_walls<float, 1>), grid, dim3(BLOCK), 0, c->stream,
+                         static_cast<float*>(c->B.rho), owner, g.nx, g.ny, g.nz, P.zeta[0], z1, P.rho0[0], r1);
+  }
+  return hipGetLastError();
+}
+
+static const uint16_t* cur_owner(lb_ctx* c) {
+  return c->has_solids ? static_cast<const uint16_t*>(c->B.owner[c->own_old]) : nullptr;
+}
+
+hipError_t launch_get_populations(lb_ctx* c, int k, int i, uint32_t first, uint32_t count,
+                                  double* out) {
+  const auto& g = c->geo;
+  const size_t off = (size_t(k) * Q + i) * g.N;
+  if (fp64(c))
+    hipLaunchKernelGGL(k_get_pop<double>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<const double*>(c->B.f[c->cur]) + off, cur_owner(c), first, count,
+                       g.nx, g.ny, g.nz, i, c->P.rho0[k], out);
+  else
+    hipLaunchKernelGGL(k_get_pop<float>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<const float*>(c->B.f[c->cur]) + off, cur_owner(c), first, count,
+                       g.nx, g.ny, g.nz, i, c->P.rho0[k], out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_populations(lb_ctx* c, int k, int i, uint32_t first, uint32_t count,
+                                  const double* in) {
+  const auto& g = c->geo;
+  const size_t off = (size_t(k) * Q + i) * g.N;
+  if (fp64(c))
+    hipLaunchKernelGGL(k_set_pop<double>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<double*>(c->B.f[c->cur]) + off, cur_owner(c), first, count,
+                       g.nx, g.ny, g.nz, i, c->P.rho0[k], in);
+  else
+    hipLaunchKernelGGL(k_set_pop<float>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<float*>(c->B.f[c->cur]) + off, cur_owner(c), first, count,
+                       g.nx, g.ny, g.nz, i, c->P.rho0[k], in);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_fields(lb_ctx* c, uint32_t first, uint32_t count, double* out) {
+  const auto& g = c->geo;
+  const auto& P = c->P;
+  const int kb = g.ncomp == 2 ? 1 : 0;
+  if (fp64(c))
+    hipLaunchKernelGGL(k_get_fields<double>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<const double*>(c->B.f[c->cur]), cur_owner(c), first, count,
+                       g.nx, g.ny, g.nz, g.ncomp, P.rho0[0], P.rho0[kb], 1.0 / P.tau[0],
+                       1.0 / P.tau[kb], out);
+  else
+    hipLaunchKernelGGL(k_get_fields<float>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<const float*>(c->B.f[c->cur]), cur_owner(c), first, count,
+                       g.nx, g.ny, g.nz, g.ncomp, P.rho0[0], P.rho0[kb], 1.0 / P.tau[0],
+                       1.0 / P.tau[kb], out);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_psi(lb_ctx* c, uint32_t first, uint32_t count, int comp, double* out) {
+  const auto& g = c->geo;
+  const size_t off = size_t(comp) * g.N;
+  if (fp64(c))
+    hipLaunchKernelGGL(k_get_psi<double>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<const double*>(c->B.rho) + off, cur_owner(c), first, count,
+                       g.nx, g.ny, g.nz, c->P.rho0[comp], out);
+  else
+    hipLaunchKernelGGL(k_get_psi<float>, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream,
+                       static_cast<const float*>(c->B.rho) + off, cur_owner(c), first, count,
+                       g.nx, g.ny, g.nz, c->P.rho0[comp], out);
+  return hipGetLastError();
+}
+
+hipError_t launch_owner_to_int(lb_ctx* c, const uint16_t* owner, uint32_t first,
+                               uint32_t count, int32_t* out) {
+  hipLaunchKernelGGL(k_owner_to_int, dim3(nblocks(count)), dim3(BLOCK), 0, c->stream, owner,
+                     first, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(lb_ctx* c, double* out_dev) {
+  const auto& g = c->geo;
+  const auto& P = c->P;
+  const int kb = g.ncomp == 2 ? 1 : 0;
+  double* partial = reinterpret_cast<double*>(wptr(c, c->wl.partials));
+  const int nb = int(std::min<uint64_t>(RED_BLOCKS, nblocks(g.N)));
+  if (fp64(c))
+    hipLaunchKernelGGL(k_reduce_partials<double>, dim3(nb), dim3(BLOCK), 0, c->stream,
+                       static_cast<const double*>(c->B.f[c->cur]), cur_owner(c), g.nx, g.ny,
+                       g.nz, g.ncomp, P.rho0[0], P.rho0[kb], 1.0 / P.tau[0], 1.0 / P.tau[kb],
+                       partial);
+  else
+    hipLaunchKernelGGL(k_reduce_partials<float>, dim3(nb), dim3(BLOCK), 0, c->stream,
+                       static_cast<const float*>(c->B.f[c->cur]), cur_owner(c), g.nx, g.ny,
+                       g.nz, g.ncomp, P.rho0[0], P.rho0[kb], 1.0 / P.tau[0], 1.0 / P.tau[kb],
+                       partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, c->stream, partial, nb, out_dev);
+  return hipGetLastError();
+}
+
+
+}  // namespace lbh

@@ -1,0 +1,123 @@
+// lb_internal.hpp -- host-side context and launch interface shared by the
+// translation units of liblbhip (not installed, not part of the C interface).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbhip.h"
+
+namespace lbh {
+
+// Scratch layout inside the caller's work buffer (byte offsets).
+struct WorkLayout {
+  size_t flags = 0;        // int32[16]: 0 speed exceeded, 1 non-finite
+  size_t partials = 0;     // double[RED_BLOCKS][RED_N]
+  size_t red_out = 0;      // double[RED_N]
+  size_t cell_count = 0;   // int32[ncell]
+  size_t cell_start = 0;   // int32[ncell + 1]
+  size_t cell_ids = 0;     // int32[P]
+  size_t staging = 0;      // double[staging_n]
+  size_t staging_n = 0;
+  size_t total = 0;
+};
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_N = 16;
+
+// Adjoint buffer layout (byte offsets), present when checkpoint_every > 0.
+struct AdjLayout {
+  size_t ckpt = 0;         // checkpoints: nckpt population buffers
+  int nckpt = 0;
+  size_t seg = 0;          // segment states: checkpoint_every population buffers
+  size_t lam[2] = {0, 0};  // adjoint populations (ping-pong), FP64 [ncomp][19][N]
+  size_t lam_a = 0;        // FP64 [ncomp][3][N]: adjoint of the SC acceleration
+  size_t lam_psi = 0;      // FP64 [ncomp][N]: adjoint of psi
+  size_t lam_rho = 0;      // FP64 [ncomp][N]: adjoint of local densities
+  size_t lam_j = 0;        // FP64 [3][N]: adjoint of the total momentum
+  size_t grad = 0;         // FP64 [3][N]: loss gradient scratch
+  size_t partials = 0;     // double[RED_BLOCKS][RED_N]
+  size_t total = 0;
+};
+
+struct Geometry {
+  uint32_t nx, ny, nz, N;
+  int ncomp;
+  int prec;      // LB_FP32 / LB_FP64
+  size_t esize;  // bytes per stored real
+};
+
+}  // namespace lbh
+
+struct lb_ctx {
+  lb_params P;
+  lb_sizes req;
+  lb_buffers B;
+  hipStream_t stream = nullptr;
+  lbh::Geometry geo;
+  lbh::WorkLayout wl;
+  lbh::AdjLayout al;
+  int cur = 0;        // population buffer holding the post-collision state f*(t-1)
+  int own_old = 0;    // owner map holding the map of the current populations
+  int nparticles = 0;
+  int64_t step = 0;
+  bool has_solids = false;  // walls or spheres present
+  bool moving = false;      // spheres present and not fixed
+  int ncell[3] = {1, 1, 1};
+  double mass = 0.0, inertia = 0.0;
+  // recording for the adjoint
+  int64_t rec_steps = 0;
+  // phase timing (HIP events on the context's stream)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
+  double phase_ms[LB_NPHASE] = {0, 0, 0, 0, 0};
+  int64_t phase_n[LB_NPHASE] = {0, 0, 0, 0, 0};
+  std::string err;
+};
+
+namespace lbh {
+
+size_t work_layout(const lb_params& p, WorkLayout& wl, int ncell_total);
+size_t adj_layout(const lb_params& p, size_t fbytes, AdjLayout& al);
+void cell_dims(const lb_params& p, int ncell[3]);
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_init_populations(lb_ctx* c, const double* rho0_dev, const double* u0_dev,
+                                   uint32_t first, uint32_t count);
+hipError_t launch_density(lb_ctx* c, const void* f);
+hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t* owner);
+hipError_t launch_fill_walls(lb_ctx* c, const uint16_t* owner);
+hipError_t launch_get_populations(lb_ctx* c, int k, int i, uint32_t first, uint32_t count,
+                                  double* out);
+hipError_t launch_set_populations(lb_ctx* c, int k, int i, uint32_t first, uint32_t count,
+                                  const double* in);
+hipError_t launch_get_fields(lb_ctx* c, uint32_t first, uint32_t count, double* out);
+hipError_t launch_get_psi(lb_ctx* c, uint32_t first, uint32_t count, int comp, double* out);
+hipError_t launch_reduce(lb_ctx* c, double* out_dev);
+hipError_t launch_owner_to_int(lb_ctx* c, const uint16_t* owner, uint32_t first,
+                               uint32_t count, int32_t* out);
+
+// particles
+hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner);   // walls + all spheres at x
+hipError_t launch_step_particles_pre(lb_ctx* c);  // unraster, raster, events, pairs, fill
+hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces);
+hipError_t launch_integrate(lb_ctx* c);
+hipError_t launch_clear_accumulators(lb_ctx* c);
+
+// adjoint
+hipError_t launch_loss(lb_ctx* c, double* L_dev, double* seedA, double* seedB);
+int backward(lb_ctx* c, const double* seedA, const double* seedB, double* dL_drhoA0,
+             double* dL_dG, double* dL_dg);
+int record_checkpoint(lb_ctx* c);
+
+inline char* wptr(lb_ctx* c, size_t off) { return static_cast<char*>(c->B.work) + off; }
+inline char* aptr(lb_ctx* c, size_t off) { return static_cast<char*>(c->B.adjoint) + off; }
+inline double* pstate(lb_ctx* c) { return static_cast<double*>(c->B.particles); }
+inline double* pacc(lb_ctx* c) {
+  return static_cast<double*>(c->B.particles) + size_t(c->P.max_particles) * 32;
+}
+
+}  // namespace lbh

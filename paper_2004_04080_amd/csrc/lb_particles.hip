@@ -1,0 +1,647 @@
+// lb_particles.hip -- sphere kernels of the gfx950 path (FP64 throughout).
+//
+// Map maintenance uses two owner maps in ping-pong: at step t the "old" map
+// holds M_{t-1} = raster(x(t-1)) and the "new" one still holds
+// raster(x(t-2)); it is cleared around x(t-2) and re-rasterised at x(t).
+// Each sphere is handled by one workgroup sweeping its bounding box, so the
+// per-sphere sums (destroyed/created nodes, frontier Shan-Chen force) are
+// block reductions written without atomics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "lb_device.hpp"
+#include "lb_internal.hpp"
+
+namespace lbh {
+
+constexpr int PBLOCK = 256;
+
+struct Box {
+  int lo[3], n[3];
+  int total;
+};
+
+// Node box covering every node within R of a centre (Sec. 2.4 staircase sphere).
+// A non-finite centre (a diverged run) gives an empty box.
+__device__ __forceinline__ Box sphere_box(const double c[3], double R) {
+  Box b;
+  b.total = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (!isfinite(c[a]) || fabs(c[a]) > 1e7) {
+      b.total = 0;
+      b.lo[a] = 0;
+      b.n[a] = 0;
+      continue;
+    }
+    b.lo[a] = int(floor(c[a] - R));
+    b.n[a] = int(ceil(c[a] + R)) - b.lo[a] + 1;
+    b.total *= b.n[a];
+  }
+  return b;
+}
+
+__device__ __forceinline__ void box_node(const Box& b, int t, int& x, int& y, int& z) {
+  x = b.lo[0] + t % b.n[0];
+  const int r = t / b.n[0];
+  y = b.lo[1] + r % b.n[1];
+  z = b.lo[2] + r / b.n[1];
+}
+
+struct PArgs {
+  uint16_t* own_new;
+  const uint16_t* own_old;
+  double* ps;
+  double* acc;
+  int32_t* flags;
+  void* fin;         // post-collision populations of the previous step
+  void* psi;
+  int nx, ny, nz;
+  uint32_t N;
+  double L[3];
+  double R;
+  double rho0[2];
+  double zeta[2];
+  double rho_fb[2];
+  double Gs;
+  int ncomp;
+  int walls;
+  int np;
+};
+
+// Sum NV doubles over the workgroup; thread 0 gets the result.
+template <int NV>
+__device__ void block_sum(double v[NV]) {
+  __shared__ double sh[NV][PBLOCK / 64];
+  const int lane = __lane_id(), wv = threadIdx.x / 64;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double s = v[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) sh[c][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double s = 0;
+      for (int w = 0; w < PBLOCK / 64; ++w) s += sh[c][w];
+      v[c] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// walls + empty fluid
+__global__ void k_map_reset(uint16_t* own, uint32_t nx, uint32_t ny, uint32_t nz, int walls) {
+  const uint32_t n = blockIdx.x * PBLOCK + threadIdx.x;
+  if (n >= nx * ny * nz) return;
+  const uint32_t z = n / (nx * ny);
+  own[n] = (walls && (z == 0 || z == nz - 1)) ? OWN_WALL : 0;
+}
+
+// Clear the nodes that sphere p holds in the map, around the centre at offset `which`.
+__global__ void __launch_bounds__(PBLOCK) k_unraster(PArgs a, int which) {
+  const int p = blockIdx.x;
+  const double* P = a.ps + size_t(p) * PSTRIDE;
+  const double c[3] = {P[which], P[which + 1], P[which + 2]};
+  const Box b = sphere_box(c, a.R);
+  const uint16_t me = uint16_t(p + 1);
+  for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
+    int x, y, z;
+    box_node(b, t, x, y, z);
+    const uint32_t n = wrap_int(x, a.nx) + a.nx * (wrap_int(y, a.ny) + a.ny * wrap_int(z, a.nz));
+    if (a.own_new[n] == me) a.own_new[n] = 0;
+  }
+}
+
+// Lowest sphere index wins a node claimed by several spheres; walls stay walls.
+__device__ __forceinline__ void claim(uint16_t* own, uint32_t n, uint16_t val) {
+  uint32_t* word = reinterpret_cast<uint32_t*>(reinterpret_cast<uintptr_t>(own + n) & ~uintptr_t(3));
+  const int shift = (reinterpret_cast<uintptr_t>(own + n) & 2) ? 16 : 0;
+  uint32_t old = *word, assumed;
+  do {
+    assumed = old;
+    const uint16_t cur = uint16_t((assumed >> shift) & 0xFFFFu);
+    if (cur == OWN_WALL || (cur != 0 && cur <= val)) return;
+    const uint32_t nw = (assumed & ~(0xFFFFu << shift)) | (uint32_t(val) << shift);
+    old = atomicCAS(word, assumed, nw);
+  } while (old != assumed);
+}
+
+// Staircase sphere: node n belongs to p when |minimg(r_n - x_p)|^2 < R^2.
+__global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which) {
+  const int p = blockIdx.x;
+  const double* P = a.ps + size_t(p) * PSTRIDE;
+  const double c[3] = {P[which], P[which + 1], P[which + 2]};
+  const Box b = sphere_box(c, a.R);
+  const double R2 = a.R * a.R;
+  for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
+    int x, y, z;
+    box_node(b, t, x, y, z);
+    const int wx = wrap_int(x, a.nx), wy = wrap_int(y, a.ny), wz = wrap_int(z, a.nz);
+    if (a.walls && (wz == 0 || wz == a.nz - 1)) continue;
+    const double dx = min_image(wx - c[0], a.L[0]);
+    const double dy = min_image(wy - c[1], a.L[1]);
+    const double dz = min_image(wz - c[2], a.L[2]);
+    if (dx * dx + dy * dy + dz * dz < R2)
+      claim(a.own_new, uint32_t(wx) + a.nx * (uint32_t(wy) + a.ny * uint32_t(wz)), uint16_t(p + 1));
+  }
+}
+
+// Fluid-node destruction (Eq. distr) and creation (Eq. creat) for sphere p.
+// Destroyed nodes hand their bare momentum sum_k j_k to the sphere; created
+// nodes get f_eq(rho_bar_k, u_w) in the slots they gather from, with rho_bar
+// the w-weighted mean over neighbours fluid in both maps.
+template <typename real>
+__global__ void __launch_bounds__(PBLOCK) k_events(PArgs a) {
+  const int p = blockIdx.x;
+  const double* P = a.ps + size_t(p) * PSTRIDE;
+  const double xc[3] = {P[PS_X], P[PS_X + 1], P[PS_X + 2]};
+  // the old centre, unwrapped next to the new one
+  double xo[3], lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    xo[d] = xc[d] + min_image(P[PS_XRA + d] - xc[d], a.L[d]);
+    lo[d] = fmin(xc[d], xo[d]);
+    hi[d] = fmax(xc[d], xo[d]);
+  }
+  Box b;
+  b.total = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (!isfinite(lo[d]) || !isfinite(hi[d]) || fabs(lo[d]) > 1e7 || fabs(hi[d]) > 1e7) {
+      b.total = 0;
+      b.lo[d] = 0;
+      b.n[d] = 0;
+      continue;
+    }
+    b.lo[d] = int(floor(lo[d] - a.R));
+    b.n[d] = int(ceil(hi[d] + a.R)) - b.lo[d] + 1;
+    b.total *= b.n[d];
+  }
+  if (threadIdx.x == 0) {
+    const double vmax = fmax(fabs(P[PS_V]), fmax(fabs(P[PS_V + 1]), fabs(P[PS_V + 2])));
+    if (!(vmax <= 0.5)) atomicOr(a.flags, 1);
+  }
+  const uint16_t me = uint16_t(p + 1);
+  real* fin = static_cast<real*>(a.fin);
+  real* psi = static_cast<real*>(a.psi);
+  const uint32_t N = a.N;
+  double v[12];
+  for (int c = 0; c < 12; ++c) v[c] = 0.0;
+  for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
+    int x, y, z;
+    box_node(b, t, x, y, z);
+    const uint32_t wx = wrap_int(x, a.nx), wy = wrap_int(y, a.ny), wz = wrap_int(z, a.nz);
+    const uint32_t n = wx + a.nx * (wy + a.ny * wz);
+    const uint16_t o = a.own_old[n], w = a.own_new[n];
+    const bool destroyed = (o == 0 && w == me);
+    const bool created = (o == me && w == 0);
+    if (!destroyed && !created) continue;
+    Nbr nb(wx, wy, wz, a.nx, a.ny, a.nz);
+    const double d[3] = {min_image(double(wx) - xc[0], a.L[0]),
+                         min_image(double(wy) - xc[1], a.L[1]),
+                         min_image(double(wz) - xc[2], a.L[2])};
+    if (destroyed) {
+      double J[3] = {0, 0, 0};
+      for (int k = 0; k < a.ncomp; ++k)
+        for (int i = 0; i < Q; ++i) {
+          const double fv = double(fin[(size_t(k) * Q + i) * N + nb.pull(i)]);
+          J[0] += fv * CX[i];
+          J[1] += fv * CY[i];
+          J[2] += fv * CZ[i];
+        }
+      v[0] += J[0];
+      v[1] += J[1];
+      v[2] += J[2];
+      v[3] += d[1] * J[2] - d[2] * J[1];
+      v[4] += d[2] * J[0] - d[0] * J[2];
+      v[5] += d[0] * J[1] - d[1] * J[0];
+    } else {
+      const double wx_ = P[PS_W], wy_ = P[PS_W + 1], wz_ = P[PS_W + 2];
+      const double uw[3] = {P[PS_V] + (wy_ * d[2] - wz_ * d[1]),
+                            P[PS_V + 1] + (wz_ * d[0] - wx_ * d[2]),
+                            P[PS_V + 2] + (wx_ * d[1] - wy_ * d[0])};
+      double wsum = 0.0, s[2] = {0.0, 0.0};
+      for (int i = 1; i < Q; ++i) {
+        const uint32_t m = nb.push(i);
+        if (a.own_old[m] != 0 || a.own_new[m] != 0) continue;
+        wsum += WQ[i];
+        for (int k = 0; k < a.ncomp; ++k) s[k] += WQ[i] * double(psi[size_t(k) * N + m]);
+      }
+      const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+      double tot = 0.0;
+      for (int k = 0; k < a.ncomp; ++k) {
+        // deviation of the created density from rho0_k
+        const double dr = wsum > 0.0 ? s[k] / wsum : a.rho_fb[k] - a.rho0[k];
+        const double rb = a.rho0[k] + dr;
+        tot += rb;
+        for (int i = 0; i < Q; ++i) {
+          const double cu = CX[i] * uw[0] + CY[i] * uw[1] + CZ[i] * uw[2];
+          fin[(size_t(k) * Q + i) * N + nb.pull(i)] =
+              real(WQ[i] * dr + WQ[i] * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        }
+        psi[size_t(k) * N + n] = real(dr);
+      }
+      const double M[3] = {tot * uw[0], tot * uw[1], tot * uw[2]};
+      v[6] -= M[0];
+      v[7] -= M[1];
+      v[8] -= M[2];
+      v[9] -= d[1] * M[2] - d[2] * M[1];
+      v[10] -= d[2] * M[0] - d[0] * M[2];
+      v[11] -= d[0] * M[1] - d[1] * M[0];
+    }
+  }
+  block_sum<12>(v);
+  if (threadIdx.x == 0) {
+    double* A = a.acc + size_t(p) * ASTRIDE;
+    for (int c = 0; c < 6; ++c) {
+      A[AC_FD + c] = v[c];
+      A[AC_FC + c] = v[6 + c];
+    }
+  }
+}
+
+// Virtual densities on the frontier of sphere p (Eq. soliddens) and the
+// Shan-Chen force those nodes feel (Eq. shanchen2), summed into F_SC, T_SC.
+template <typename real>
+__global__ void __launch_bounds__(PBLOCK) k_fill_sphere(PArgs a) {
+  const int p = blockIdx.x;
+  const double* P = a.ps + size_t(p) * PSTRIDE;
+  const double xc[3] = {P[PS_X], P[PS_X + 1], P[PS_X + 2]};
+  const Box b = sphere_box(xc, a.R);
+  const uint16_t me = uint16_t(p + 1);
+  real* psi = static_cast<real*>(a.psi);
+  const uint32_t N = a.N;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
+    int x, y, z;
+    box_node(b, t, x, y, z);
+    const uint32_t wx = wrap_int(x, a.nx), wy = wrap_int(y, a.ny), wz = wrap_int(z, a.nz);
+    const uint32_t n = wx + a.nx * (wy + a.ny * wz);
+    if (a.own_new[n] != me) continue;
+    Nbr nb(wx, wy, wz, a.nx, a.ny, a.nz);
+    double wsum = 0.0, s[2] = {0, 0}, Ws[3] = {0, 0, 0}, g[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int i = 1; i < Q; ++i) {
+      const uint32_t m = nb.push(i);
+      if (a.own_new[m] != 0) continue;
+      wsum += WQ[i];
+      Ws[0] += WQ[i] * CX[i];
+      Ws[1] += WQ[i] * CY[i];
+      Ws[2] += WQ[i] * CZ[i];
+      for (int k = 0; k < a.ncomp; ++k) {
+        const double dp = double(psi[size_t(k) * N + m]);
+        s[k] += WQ[i] * dp;
+        g[k][0] += WQ[i] * dp * CX[i];
+        g[k][1] += WQ[i] * dp * CY[i];
+        g[k][2] += WQ[i] * dp * CZ[i];
+      }
+    }
+    if (wsum == 0.0) continue;
+    double dv[2];
+    for (int k = 0; k < a.ncomp; ++k) {
+      dv[k] = a.zeta[k] * a.rho0[k] + (1.0 + a.zeta[k]) * s[k] / wsum;
+      psi[size_t(k) * N + n] = real(dv[k]);
+    }
+    if (a.ncomp == 2) {
+      double F[3] = {0, 0, 0};
+      for (int k = 0; k < 2; ++k) {
+        const int kb = 1 - k;
+        const double pk = a.rho0[k] + dv[k];
+        for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + g[kb][c]);
+      }
+      const double d[3] = {min_image(double(wx) - xc[0], a.L[0]),
+                           min_image(double(wy) - xc[1], a.L[1]),
+                           min_image(double(wz) - xc[2], a.L[2])};
+      v[0] += F[0];
+      v[1] += F[1];
+      v[2] += F[2];
+      v[3] += d[1] * F[2] - d[2] * F[1];
+      v[4] += d[2] * F[0] - d[0] * F[2];
+      v[5] += d[0] * F[1] - d[1] * F[0];
+    }
+  }
+  block_sum<6>(v);
+  if (threadIdx.x == 0 && a.acc) {
+    double* A = a.acc + size_t(p) * ASTRIDE;
+    for (int c = 0; c < 6; ++c) A[AC_FSC + c] = v[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hertz contacts (Eq. hertzpot, repulsive reading) through a uniform cell list.
+// ---------------------------------------------------------------------------
+struct CellArgs {
+  const double* ps;
+  double* acc;
+  int32_t* count;
+  int32_t* start;
+  int32_t* ids;
+  int nc[3];
+  double cs[3];   // cell side
+  double L[3];
+  int np;
+  double K, d0, rcap;
+  int walls;
+  double zlo, zhi;
+};
+
+__device__ __forceinline__ int cell_of(const CellArgs& a, const double* x) {
+  int ci[3];
+  for (int d = 0; d < 3; ++d) {
+    int c = int(floor(x[d] / a.cs[d]));
+    ci[d] = c < 0 ? 0 : (c >= a.nc[d] ? a.nc[d] - 1 : c);
+  }
+  return ci[0] + a.nc[0] * (ci[1] + a.nc[1] * ci[2]);
+}
+
+__global__ void k_cell_count(CellArgs a) {
+  const int p = blockIdx.x * PBLOCK + threadIdx.x;
+  if (p >= a.np) return;
+  atomicAdd(&a.count[cell_of(a, a.ps + size_t(p) * PSTRIDE)], 1);
+}
+
+// exclusive scan of count into start (single workgroup), then clear count
+__global__ void __launch_bounds__(1024) k_cell_scan(int32_t* count, int32_t* start, int ncell) {
+  __shared__ int32_t sh[1024];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ncell; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int32_t v = i < ncell ? count[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < ncell) {
+      start[i] = carry + sh[threadIdx.x] - v;
+      count[i] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += sh[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) start[ncell] = carry;
+}
+
+__global__ void k_cell_fill(CellArgs a) {
+  const int p = blockIdx.x * PBLOCK + threadIdx.x;
+  if (p >= a.np) return;
+  const int c = cell_of(a, a.ps + size_t(p) * PSTRIDE);
+  const int slot = atomicAdd(&a.count[c], 1);
+  a.ids[a.start[c] + slot] = p;
+}
+
+// sort the ids of each cell so that the pair sums have a fixed order
+__global__ void k_cell_sort(CellArgs a, int ncell) {
+  const int c = blockIdx.x * PBLOCK + threadIdx.x;
+  if (c >= ncell) return;
+  const int b = a.start[c], e = a.start[c + 1];
+  for (int i = b + 1; i < e; ++i) {
+    const int v = a.ids[i];
+    int j = i - 1;
+    while (j >= b && a.ids[j] > v) {
+      a.ids[j + 1] = a.ids[j];
+      --j;
+    }
+    a.ids[j + 1] = v;
+  }
+}
+
+__device__ __forceinline__ double hertz_mag(double r, double K, double d0, double rcap) {
+  if (r >= d0) return 0.0;
+  const double h = d0 - fmax(r, rcap);
+  return 2.5 * K * h * sqrt(h);
+}
+
+__global__ void k_pairs(CellArgs a) {
+  const int p = blockIdx.x * PBLOCK + threadIdx.x;
+  if (p >= a.np) return;
+  const double* xp = a.ps + size_t(p) * PSTRIDE;
+  int ci[3];
+  for (int d = 0; d < 3; ++d) {
+    int c = int(floor(xp[d] / a.cs[d]));
+    ci[d] = c < 0 ? 0 : (c >= a.nc[d] ? a.nc[d] - 1 : c);
+  }
+  double F[3] = {0, 0, 0};
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    // visit each neighbouring cell once, also when there are fewer than 3 cells
+    lo[d] = a.nc[d] >= 3 ? -1 : 0;
+    hi[d] = a.nc[d] >= 3 ? 1 : a.nc[d] - 1;
+  }
+  for (int dz = lo[2]; dz <= hi[2]; ++dz)
+    for (int dy = lo[1]; dy <= hi[1]; ++dy)
+      for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+        const int cx = wrap_int(ci[0] + dx, a.nc[0]), cy = wrap_int(ci[1] + dy, a.nc[1]),
+                  cz = wrap_int(ci[2] + dz, a.nc[2]);
+        const int c = cx + a.nc[0] * (cy + a.nc[1] * cz);
+        for (int s = a.start[c]; s < a.start[c + 1]; ++s) {
+          const int q = a.ids[s];
+          if (q == p) continue;
+          const double* xq = a.ps + size_t(q) * PSTRIDE;
+          const double d[3] = {min_image(xq[0] - xp[0], a.L[0]), min_image(xq[1] - xp[1], a.L[1]),
+                               min_image(xq[2] - xp[2], a.L[2])};
+          const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          const double mag = hertz_mag(r, a.K, a.d0, a.rcap);
+          if (mag == 0.0) continue;
+          for (int e = 0; e < 3; ++e) F[e] -= mag * d[e] / r;
+        }
+      }
+  if (a.walls) {  // mirror image across each wall plane
+    F[2] += hertz_mag(2.0 * (xp[2] - a.zlo), a.K, a.d0, a.rcap);
+    F[2] -= hertz_mag(2.0 * (a.zhi - xp[2]), a.K, a.d0, a.rcap);
+  }
+  double* A = a.acc + size_t(p) * ASTRIDE;
+  for (int e = 0; e < 3; ++e) A[AC_FH + e] = F[e];
+}
+
+// ---------------------------------------------------------------------------
+// Newton-Euler update (Eq. lf) with the half-step fluid force average and
+// Svanberg's implicit mid-step quaternion (Eq. quatder, svanimpl).
+// ---------------------------------------------------------------------------
+__device__ void quat_rate(const double q[4], const double w[3], double out[4]) {
+  const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+  // body-frame angular velocity w* = R(q)^T w with the (unnormalised) matrix R(q)
+  const double R00 = q0 * q0 + q1 * q1 - q2 * q2 - q3 * q3, R01 = 2 * (q1 * q2 - q0 * q3),
+               R02 = 2 * (q1 * q3 + q0 * q2);
+  const double R10 = 2 * (q1 * q2 + q0 * q3), R11 = q0 * q0 - q1 * q1 + q2 * q2 - q3 * q3,
+               R12 = 2 * (q2 * q3 - q0 * q1);
+  const double R20 = 2 * (q1 * q3 - q0 * q2), R21 = 2 * (q2 * q3 + q0 * q1),
+               R22 = q0 * q0 - q1 * q1 - q2 * q2 + q3 * q3;
+  const double bx = R00 * w[0] + R10 * w[1] + R20 * w[2];
+  const double by = R01 * w[0] + R11 * w[1] + R21 * w[2];
+  const double bz = R02 * w[0] + R12 * w[1] + R22 * w[2];
+  out[0] = 0.5 * (-q1 * bx - q2 * by - q3 * bz);
+  out[1] = 0.5 * (q0 * bx - q3 * by + q2 * bz);
+  out[2] = 0.5 * (q3 * bx + q0 * by - q1 * bz);
+  out[3] = 0.5 * (-q2 * bx + q1 * by + q0 * bz);
+}
+
+__global__ void k_integrate(double* ps, const double* acc, int np, double mass, double inertia,
+                            double Lx, double Ly, double Lz, int rotate) {
+  const int p = blockIdx.x * PBLOCK + threadIdx.x;
+  if (p >= np) return;
+  double* P = ps + size_t(p) * PSTRIDE;
+  const double* A = acc + size_t(p) * ASTRIDE;
+  if (P[PS_HAVEPREV] == 0.0)
+    for (int e = 0; e < 3; ++e) {
+      P[PS_FPREV + e] = A[AC_FLIQ + e];
+      P[PS_TPREV + e] = A[AC_TLIQ + e];
+    }
+  const double L[3] = {Lx, Ly, Lz};
+  double w[3];
+  for (int e = 0; e < 3; ++e) {
+    const double F = 0.5 * (P[PS_FPREV + e] + A[AC_FLIQ + e]) + A[AC_FD + e] + A[AC_FC + e] +
+                     A[AC_FH + e] + A[AC_FSC + e];
+    const double T = 0.5 * (P[PS_TPREV + e] + A[AC_TLIQ + e]) + A[AC_TD + e] + A[AC_TC + e] +
+                     A[AC_TSC + e];
+    P[PS_V + e] += F / mass;
+    P[PS_XRB + e] = P[PS_XRA + e];
+    P[PS_XRA + e] = P[PS_X + e];
+    double x = fmod(P[PS_X + e] + P[PS_V + e], L[e]);
+    if (x < 0) x += L[e];
+    if (x >= L[e]) x -= L[e];
+    P[PS_X + e] = x;
+    if (rotate) P[PS_W + e] += T / inertia;
+    w[e] = P[PS_W + e];
+    P[PS_FPREV + e] = A[AC_FLIQ + e];
+    P[PS_TPREV + e] = A[AC_TLIQ + e];
+  }
+  P[PS_HAVEPREV] = 1.0;
+  if (!rotate) return;
+  double q[4] = {P[PS_Q], P[PS_Q + 1], P[PS_Q + 2], P[PS_Q + 3]};
+  double qd[4], qh[4], qn[4];
+  quat_rate(q, w, qd);
+  for (int c = 0; c < 4; ++c) qh[c] = q[c] + 0.5 * qd[c];
+  for (int it = 0; it < 50; ++it) {
+    quat_rate(qh, w, qn);
+    double diff = 0.0;
+    for (int c = 0; c < 4; ++c) diff = fmax(diff, fabs(qn[c] - qd[c]));
+    for (int c = 0; c < 4; ++c) {
+      qd[c] = qn[c];
+      qh[c] = q[c] + 0.5 * qd[c];
+    }
+    if (diff <= 1e-14) break;
+  }
+  double nrm = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    q[c] += qd[c];
+    nrm += q[c] * q[c];
+  }
+  nrm = sqrt(nrm);
+  for (int c = 0; c < 4; ++c) P[PS_Q + c] = q[c] / nrm;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static PArgs pargs(lb_ctx* c, uint16_t* own_new, const uint16_t* own_old) {
+  PArgs a;
+  a.own_new = own_new;
+  a.own_old = own_old;
+  a.ps = pstate(c);
+  a.acc = pacc(c);
+  a.flags = reinterpret_cast<int32_t*>(wptr(c, c->wl.flags));
+  a.fin = c->B.f[c->cur];
+  a.psi = c->B.rho;
+  a.nx = int(c->geo.nx);
+  a.ny = int(c->geo.ny);
+  a.nz = int(c->geo.nz);
+  a.N = c->geo.N;
+  a.L[0] = c->geo.nx;
+  a.L[1] = c->geo.ny;
+  a.L[2] = c->geo.nz;
+  a.R = c->P.radius;
+  a.ncomp = c->geo.ncomp;
+  for (int k = 0; k < 2; ++k) {
+    a.rho0[k] = c->P.rho0[k];
+    a.zeta[k] = c->P.zeta[k];
+    a.rho_fb[k] = c->P.rho_fallback[k];
+  }
+  a.Gs = c->P.G * c->P.sc_norm;
+  a.walls = c->P.walls;
+  a.np = c->nparticles;
+  return a;
+}
+
+hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner) {
+  const auto& g = c->geo;
+  hipLaunchKernelGGL(k_map_reset, dim3((g.N + PBLOCK - 1) / PBLOCK), dim3(PBLOCK), 0, c->stream,
+                     owner, g.nx, g.ny, g.nz, c->P.walls);
+  if (c->nparticles > 0)
+    hipLaunchKernelGGL(k_raster, dim3(c->nparticles), dim3(PBLOCK), 0, c->stream,
+                       pargs(c, owner, owner), int(PS_X));
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_accumulators(lb_ctx* c) {
+  return hipMemsetAsync(pacc(c), 0, size_t(c->nparticles) * ASTRIDE * sizeof(double), c->stream);
+}
+
+hipError_t launch_step_particles_pre(lb_ctx* c) {
+  uint16_t* own_new = static_cast<uint16_t*>(c->B.owner[1 - c->own_old]);
+  const uint16_t* own_old = static_cast<const uint16_t*>(c->B.owner[c->own_old]);
+  const PArgs a = pargs(c, own_new, own_old);
+  const dim3 gp(c->nparticles), bp(PBLOCK);
+  hipLaunchKernelGGL(k_unraster, gp, bp, 0, c->stream, a, int(PS_XRB));
+  hipLaunchKernelGGL(k_raster, gp, bp, 0, c->stream, a, int(PS_X));
+  if (c->geo.prec == LB_FP64)
+    hipLaunchKernelGGL(k_events<double>, gp, bp, 0, c->stream, a);
+  else
+    hipLaunchKernelGGL(k_events<float>, gp, bp, 0, c->stream, a);
+  // Hertz pairs through the cell list
+  CellArgs ca;
+  ca.ps = pstate(c);
+  ca.acc = pacc(c);
+  ca.count = reinterpret_cast<int32_t*>(wptr(c, c->wl.cell_count));
+  ca.start = reinterpret_cast<int32_t*>(wptr(c, c->wl.cell_start));
+  ca.ids = reinterpret_cast<int32_t*>(wptr(c, c->wl.cell_ids));
+  int ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    ca.nc[d] = c->ncell[d];
+    ncell *= c->ncell[d];
+    ca.L[d] = d == 0 ? c->geo.nx : d == 1 ? c->geo.ny : c->geo.nz;
+    ca.cs[d] = ca.L[d] / c->ncell[d];
+  }
+  ca.np = c->nparticles;
+  ca.K = c->P.hertz_K;
+  ca.d0 = c->P.hertz_d0;
+  ca.rcap = c->P.hertz_rcap;
+  ca.walls = c->P.walls;
+  ca.zlo = 0.5;
+  ca.zhi = c->geo.nz - 1.5;
+  hipError_t e = hipMemsetAsync(ca.count, 0, size_t(ncell) * sizeof(int32_t), c->stream);
+  if (e != hipSuccess) return e;
+  const dim3 gt((c->nparticles + PBLOCK - 1) / PBLOCK);
+  hipLaunchKernelGGL(k_cell_count, gt, bp, 0, c->stream, ca);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, c->stream, ca.count, ca.start, ncell);
+  hipLaunchKernelGGL(k_cell_fill, gt, bp, 0, c->stream, ca);
+  hipLaunchKernelGGL(k_cell_sort, dim3((ncell + PBLOCK - 1) / PBLOCK), bp, 0, c->stream, ca, ncell);
+  hipLaunchKernelGGL(k_pairs, gt, bp, 0, c->stream, ca);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces) {
+  PArgs a = pargs(c, const_cast<uint16_t*>(owner), owner);
+  if (!forces) a.acc = nullptr;
+  if (c->geo.prec == LB_FP64)
+    hipLaunchKernelGGL(k_fill_sphere<double>, dim3(c->nparticles), dim3(PBLOCK), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL(k_fill_sphere<float>, dim3(c->nparticles), dim3(PBLOCK), 0, c->stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_integrate(lb_ctx* c) {
+  hipLaunchKernelGGL(k_integrate, dim3((c->nparticles + PBLOCK - 1) / PBLOCK), dim3(PBLOCK), 0,
+                     c->stream, pstate(c), pacc(c), c->nparticles, c->mass, c->inertia,
+                     double(c->geo.nx), double(c->geo.ny), double(c->geo.nz), c->P.rotate);
+  return hipGetLastError();
+}
+
+}  // namespace lbh

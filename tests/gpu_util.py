@@ -1,0 +1,122 @@
+"""Helpers of the GPU parity tests: build the oracle and the HIP path from one
+parameter set and the same seeded inputs, and measure their differences.
+
+Error measure (per field): eps(X) = max|X_gpu - X_ref| / max|X_ref| over the
+fluid nodes, for X in {f, df = f - w rho0, rho_A, rho_B, phi = rho_A - rho_B, u}.
+The deviations df are ~1e-3 of f, so FP64 rounding of full populations (the
+oracle works on f) shows in eps(df) after many steps; df is gated at short
+horizons and f at every horizon.
+Sphere forces are compared against the sum over links of |F_link|.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def gpu_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+requires_gpu = pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+
+_COMMON = ("ncomp", "tau", "G", "sc_norm", "g", "walls", "wall_u_lo", "wall_u_hi", "radius",
+           "particle_density", "hertz_K", "hertz_d0", "hertz_rcap", "zeta", "rho_fallback",
+           "rotate", "particles_fixed")
+
+
+def make_pair(shape, rho, u0=None, x=None, v=None, w=None, precision="fp64", **kw):
+    """(oracle, lattice) with identical parameters and initial state."""
+    from paper_2004_04080_amd import Lattice, Params
+    common = {k: kw[k] for k in _COMMON if k in kw}
+    po = O.Params(*shape, **common)
+    extra = {k: kw[k] for k in ("checkpoint_every", "max_record_steps", "rho0") if k in kw}
+    npart = 0 if x is None else len(x)
+    pg = Params(*shape, precision=precision, max_particles=npart, **common, **extra)
+    o = O.Oracle(po, rho, u0)
+    lat = Lattice(pg, rho, u0)
+    if npart:
+        o.add_particles(x, v, w)
+        lat.add_particles(x, v, w)
+    return o, lat
+
+
+def perm_gpu_for_oracle() -> np.ndarray:
+    """GPU direction index of each oracle direction."""
+    from paper_2004_04080_amd import lattice
+    co, _ = O.lattice()
+    cg, _ = lattice()
+    return np.array([int(np.where((cg == c).all(1))[0][0]) for c in co])
+
+
+def _eps(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def compare(o, lat, rho0=(1.0, 1.0)) -> dict:
+    """Errors of the HIP state against the oracle state (both at the same time)."""
+    perm = perm_gpu_for_oracle()
+    _, w = O.lattice()
+    own_o = o.owner()
+    own_g = lat.owner()
+    fluid = own_o == 0
+    K = o.params.ncomp
+    fo = o.f()[:, :, fluid]
+    fg = lat.populations()[:, perm, :][:, :, fluid]
+    ref = np.array(rho0[:K])[:, None, None] * w[None, :, None]
+    out = {"owner_equal": bool(np.array_equal(own_o, own_g)),
+           "f": _eps(fg, fo),
+           "df": _eps(fg - ref, fo - ref)}
+    ro = o.rho()[:, fluid]
+    rg, ug = lat.fields()
+    rg = rg[:, fluid]
+    for k in range(K):
+        out[f"rho{k}"] = _eps(rg[k], ro[k])
+    if K == 2:
+        out["phi"] = _eps(rg[0] - rg[1], ro[0] - ro[1])
+    out["u"] = _eps(ug[fluid], o.u()[fluid])
+    return out
+
+
+def compare_particles(o, lat) -> dict:
+    ro = o.particles()
+    rg = lat.particles()
+    out = {}
+    if ro.shape[0] == 0:
+        return out
+    R = O.REC
+    L = np.array([o.params.nx, o.params.ny, o.params.nz], dtype=float)
+    dx = rg[:, R["x"]:R["x"] + 3] - ro[:, R["x"]:R["x"] + 3]
+    dx -= L * np.round(dx / L)
+    out["x"] = float(np.abs(dx).max())
+    for key, n in (("v", 3), ("w", 3), ("q", 4)):
+        out[key] = _eps(rg[:, R[key]:R[key] + n], ro[:, R[key]:R[key] + n])
+    scale = max(ro[:, R["flabs"]].max(), 1e-30)
+    for key in ("Fliq", "Tliq", "Fd", "Td", "Fc", "Tc", "FH", "FSC", "TSC"):
+        out[key] = float(np.abs(rg[:, R[key]:R[key] + 3] - ro[:, R[key]:R[key] + 3]).max() / scale)
+    out["flabs"] = _eps(rg[:, R["flabs"]], ro[:, R["flabs"]])
+    return out
+
+
+def sync_state(o, lat):
+    """Give the oracle the exact state of the HIP path (populations rounded to
+    the HIP storage precision, sphere records, map)."""
+    perm = perm_gpu_for_oracle()
+    f = lat.populations()[:, perm, :]
+    o.set_f(f)
+    o.set_owner(lat.owner())
+    if o.num_particles():
+        rec = o.particles()
+        rg = lat.particles()
+        R = O.REC
+        for key, n in (("x", 3), ("v", 3), ("w", 3), ("q", 4), ("Fprev", 3), ("Tprev", 3)):
+            rec[:, R[key]:R[key] + n] = rg[:, R[key]:R[key] + n]
+        rec[:, R["have_prev"]] = rg[:, R["have_prev"]]
+        o.set_particle_state(rec)

@@ -1,0 +1,164 @@
+"""HIP path against the oracle, element by element, through the C interface.
+
+Tolerances (relative, per field, see gpu_util.compare): FP64 <= 1e-12 at the
+stated horizons; FP32 (deviation storage) <= 1e-5 for one step from a common
+FP32-representable state and over short trajectories. Sphere forces are
+compared against the sum over links of |F_link|; their FP64 atomic sums are
+order dependent at the 1e-14 level.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import compare, compare_particles, make_pair, requires_gpu, sync_state
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _check(o, lat, tol, what="", df_gate=True):
+    """Gate every field at tol; df (deviations) only when df_gate (short horizons)."""
+    e = compare(o, lat)
+    print(what, {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in e.items()}, flush=True)
+    assert e.pop("owner_equal")
+    if not df_gate:
+        e.pop("df")
+    for k, v in e.items():
+        assert v <= tol, (what, k, v)
+    return e
+
+
+def test_c1_shear_wave_fp64_200_steps():
+    w = synth.workload("C1")
+    u0 = synth.shear_wave_velocity(w.nx, w.ny, w.nz)
+    rho = np.ones((1, w.N))
+    o, lat = make_pair((w.nx, w.ny, w.nz), rho, u0, ncomp=1, tau=w.tau)
+    done = 0
+    for h in (1, 10, 200):
+        o.step(h - done)
+        lat.step(h - done)
+        done = h
+        _check(o, lat, TOL64, f"C1 t={h}", df_gate=h <= 10)
+    ob = lat.observables()
+    assert abs(ob.mass[0] - w.N) / w.N < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(19, 13, 11), (33, 7, 5)])
+def test_two_fluids_fp64_odd_boxes(shape):
+    w = synth.Workload("odd", *shape, seed=synth.BASE_SEED + 21)
+    rho = w.densities()
+    o, lat = make_pair(shape, rho, G=0.65, g=(2e-5, -1e-5, 3e-5), tau=(1.0, 1.0))
+    done = 0
+    for h in (1, 10, 100):
+        o.step(h - done)
+        lat.step(h - done)
+        done = h
+        _check(o, lat, TOL64, f"2c {shape} t={h}", df_gate=h <= 10)
+
+
+def test_two_fluids_unequal_tau_fp64():
+    shape = (12, 10, 9)
+    w = synth.Workload("ut", *shape, seed=synth.BASE_SEED + 22)
+    o, lat = make_pair(shape, w.densities(), G=0.7, tau=(0.8, 1.3))
+    for h in (1, 20):
+        o.step(h if h == 1 else 19)
+        lat.step(h if h == 1 else 19)
+        _check(o, lat, TOL64, f"unequal tau t={h}")
+
+
+def test_two_fluids_fp32_step_and_trajectory():
+    shape = (24, 17, 13)
+    w = synth.Workload("f32", *shape, seed=synth.BASE_SEED + 23)
+    o, lat = make_pair(shape, w.densities(), precision="fp32", G=0.65)
+    # trajectory from the common initial state
+    o.step(10)
+    lat.step(10)
+    _check(o, lat, TOL32, "fp32 trajectory t=10")
+    # step parity from a state both hold exactly
+    lat.step(190)
+    sync_state(o, lat)
+    o.step(1)
+    lat.step(1)
+    _check(o, lat, TOL32, "fp32 step t=201")
+
+
+def test_walls_moving_fp64():
+    shape = (10, 9, 14)
+    w = synth.Workload("wall", *shape, seed=synth.BASE_SEED + 24)
+    o, lat = make_pair(shape, w.densities(), G=0.65, walls=True, wall_u_lo=(-0.01, 0.002, 0.0),
+                       wall_u_hi=(0.01, 0.0, 0.0), g=(1e-5, 0, 0), zeta=(0.05, -0.05))
+    for h in (1, 10, 50):
+        o.step(1 if h == 1 else (9 if h == 10 else 40))
+        lat.step(1 if h == 1 else (9 if h == 10 else 40))
+        _check(o, lat, TOL64, f"walls t={h}", df_gate=h <= 10)
+
+
+def _spheres(shape, n, R, seed, walls=False):
+    w = synth.Workload("sph", *shape, nparticles=n, radius=R, seed=seed, walls=walls)
+    rng = np.random.default_rng(seed)
+    x = w.centres()
+    v = 0.06 * (2 * rng.random((n, 3)) - 1)
+    om = 0.02 * (2 * rng.random((n, 3)) - 1)
+    return w, x, v, om
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_moving_spheres_fp64(walls):
+    shape = (26, 22, 24)
+    w, x, v, om = _spheres(shape, 6, 3.0, synth.BASE_SEED + 25, walls)
+    kw = dict(G=0.65, radius=3.0, particle_density=2.0, zeta=(0.1, -0.1))
+    if walls:
+        kw.update(walls=True, wall_u_lo=(-0.01, 0, 0), wall_u_hi=(0.01, 0, 0))
+    o, lat = make_pair(shape, w.densities(), x=x, v=v, w=om, **kw)
+    done = 0
+    events = 0
+    for h in (1, 5, 20):
+        own0 = o.owner()
+        assert o.step(h - done) == 0
+        lat.step(h - done)
+        events += int((own0 != o.owner()).sum())
+        done = h
+        _check(o, lat, 1e-11, f"spheres t={h}", df_gate=h <= 10)
+        ep = compare_particles(o, lat)
+        print("particles", {k: f"{v:.1e}" for k, v in ep.items()}, flush=True)
+        assert ep["x"] < 1e-11 and ep["v"] < 1e-11 and ep["w"] < 1e-11 and ep["q"] < 1e-12
+        for k in ("Fliq", "Tliq", "Fd", "Td", "Fc", "Tc", "FH", "FSC", "TSC"):
+            assert ep[k] < 1e-12, k
+    assert events > 0
+    assert lat.observables().flags == 0
+
+
+def test_moving_spheres_fp32_step_parity():
+    shape = (30, 28, 26)
+    w, x, v, om = _spheres(shape, 8, 3.5, synth.BASE_SEED + 26)
+    o, lat = make_pair(shape, w.densities(), x=x, v=v, w=om, precision="fp32", G=0.65,
+                       radius=3.5, particle_density=2.0)
+    lat.step(30)
+    sync_state(o, lat)
+    for t in range(3):
+        o.step(1)
+        lat.step(1)
+        _check(o, lat, TOL32, f"fp32 spheres step {t}")
+        ep = compare_particles(o, lat)
+        print("particles", {k: f"{v:.1e}" for k, v in ep.items()}, flush=True)
+        for k in ("Fliq", "Tliq", "FSC", "TSC", "Fd", "Fc"):
+            assert ep[k] < 1e-5, k
+        assert ep["x"] < 1e-6
+
+
+def test_fixed_spheres_fp64_and_loss():
+    shape = (20, 18, 16)
+    w, x, _, _ = _spheres(shape, 3, 3.0, synth.BASE_SEED + 27)
+    o, lat = make_pair(shape, w.densities(), x=x, G=0.65, radius=3.0, particles_fixed=True,
+                       g=(1e-6, 0, 0))
+    o.step(15)
+    lat.step(15)
+    _check(o, lat, TOL64, "fixed spheres t=15", df_gate=False)
+    assert abs(lat.loss() - o.loss()) <= 1e-12 * o.loss()
+    psi_g = lat.psi()
+    rho_o = o.rho()
+    fluid = o.owner() == 0
+    assert np.abs(psi_g[:, fluid] - rho_o[:, fluid]).max() < 1e-12
