@@ -99,8 +99,7 @@ def roofline(w, res, es):
     nfl, nlinks, N = res["fluid_nodes"], res["links"], w.N
     bytes_launch = (nfl * 2 * K * 19 * es      # gather + store of the populations
                     + N * K * es               # pseudo-potential field, read once
-                    + N * 2                    # owner map
-                    + nlinks * K * es)         # reflected values written into solid slots
+                    + (N * 2 if w.walls or w.nparticles else 0))   # owner map
     ms, n = res["phases"]["collide"]
     avg_ms = ms / max(n, 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9

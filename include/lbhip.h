@@ -234,7 +234,8 @@ int lb_sync(struct lb_ctx* ctx);
  * and starts recording, lb_timing(ctx, 0) stops. lb_timing_read synchronises
  * and returns the summed milliseconds and launch counts per phase:
  * 0 moments (density), 1 sphere map/events/pairs, 2 virtual-density fills,
- * 3 collide-stream-bounce-back, 4 sphere integration. */
+ * 3 collide-stream-bounce-back with the link momentum exchange,
+ * 4 sphere integration. */
 #define LB_NPHASE 5
 int lb_timing(struct lb_ctx* ctx, int enable);
 int lb_timing_read(struct lb_ctx* ctx, double ms[LB_NPHASE], int64_t count[LB_NPHASE]);

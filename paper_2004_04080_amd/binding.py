@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "liblbhip.so")
+# LBHIP_LIB selects another build of the same sources (timing experiments)
+LIB_PATH = os.environ.get("LBHIP_LIB", os.path.join(HERE, "_lib", "liblbhip.so"))
 
 LB_OK = 0
 LB_E_ARG, LB_E_SHAPE, LB_E_OVERLAP, LB_E_CAPACITY = -1, -2, -3, -4

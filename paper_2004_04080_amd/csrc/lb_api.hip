@@ -6,7 +6,7 @@
 //   density (pull-gather moments)                      -> psi
 //   [spheres] clear accumulators; [moving] unraster, raster, events, Hertz pairs
 //   [spheres] frontier fill + Shan-Chen on solids; [walls] wall fill
-//   collide (SC + EDM + store + moving bounce-back + link reduction)
+//   collide (SC + EDM + store + moving bounce-back + link momentum exchange)
 //   [moving] integrate; swap buffers and maps
 #include <hip/hip_runtime.h>
 

@@ -68,6 +68,18 @@ struct Nbr {
   }
 };
 
+// Periodic neighbour (x+cx, y+cy, z+cz) for offsets only known at run time,
+// by plain arithmetic (indexing the Nbr tables with run-time offsets would
+// force them out of registers).
+__device__ __forceinline__ uint32_t nbr_dyn(uint32_t x, uint32_t y, uint32_t z, int cx, int cy,
+                                            int cz, uint32_t nx, uint32_t ny, uint32_t nz) {
+  int a = int(x) + cx, b = int(y) + cy, c = int(z) + cz;
+  a = a < 0 ? a + int(nx) : (a >= int(nx) ? a - int(nx) : a);
+  b = b < 0 ? b + int(ny) : (b >= int(ny) ? b - int(ny) : b);
+  c = c < 0 ? c + int(nz) : (c >= int(nz) ? c - int(nz) : c);
+  return uint32_t(a) + nx * (uint32_t(b) + ny * uint32_t(c));
+}
+
 __device__ __forceinline__ void node_xyz(uint32_t n, uint32_t nx, uint32_t ny, uint32_t& x,
                                          uint32_t& y, uint32_t& z) {
   x = n % nx;

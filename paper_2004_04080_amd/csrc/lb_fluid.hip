@@ -91,12 +91,25 @@ struct CollideArgs {
   double omega;       // relaxation rate when the relaxation times are equal
   int equal_tau;
   double wall_lo[3], wall_hi[3];
-  double L[3];
+  double L[3], invL[3];
+  uint32_t ntx, nty, tiles, tiles_per_xcd;  // tiling of the collide grid
 };
+
+// Packed direction tables for a direction index that varies per lane:
+// two bits (c + 1) per direction and axis.
+constexpr uint64_t pack_dir(const int* c) {
+  uint64_t v = 0;
+  for (int i = 0; i < Q; ++i) v |= uint64_t(c[i] + 1) << (2 * i);
+  return v;
+}
+constexpr uint64_t PCX = pack_dir(CX), PCY = pack_dir(CY), PCZ = pack_dir(CZ);
+__device__ __forceinline__ int dir_c(uint64_t packed, int i) { return int((packed >> (2 * i)) & 3) - 1; }
+// opposite direction in the library's order (1<->2, 3<->4, 5<->6, 7<->8, 9..13<->14..18)
+__device__ __forceinline__ int dir_opp(int i) { return i <= 8 ? ((i - 1) ^ 1) + 1 : (i <= 13 ? i + 5 : i - 5); }
 
 // Wave-level segmented reduction of per-lane link force/torque contributions
 // keyed by sphere id, then one FP64 atomic per (wave, sphere, component).
-// Every lane of the wave must call this (inactive contributions use pid < 0).
+// Every lane of the wave must call this (lanes without contributions pass pid < 0).
 __device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, double v[7]) {
   const int lane = __lane_id();
   uint64_t pending = __ballot(pid >= 0);
@@ -123,188 +136,235 @@ __device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, d
 }
 
 // ---------------------------------------------------------------------------
-// The fused step for one fluid node: pull-gather (Eq. bgk2), moments and
-// mixture velocity (Eq. rho, vel, scvel), Shan-Chen acceleration from the
+// The fused step for one node: pull-gather (Eq. bgk2), moments and mixture
+// velocity (Eq. rho, vel, scvel), Shan-Chen acceleration from the
 // pseudo-potential of the neighbours (Eq. shanchen), EDM collision
-// (Eq. lbsbgk), store; then for every link ending on a solid node the
-// moving-wall reflection (Eq. LADDFLBE, UPI) into that node's slot and the
-// link momentum exchange (Eq. LADDFORCE) reduced per sphere.
+// (Eq. lbsbgk) and store; then, for every link ending on a solid node, the
+// moving-wall reflection (Eq. bbv, LADDFLBE, UPI) into the slot of that node
+// which this node gathers next step, and the link momentum exchange
+// (Eq. LADDFORCE) summed per sphere (Eq. FORCEPARTEQ, TORQUEPARTEQ).
 // In deviation form with E_i(v) = w_i rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v):
 //   df*_i = w_i drho + E_i(u + a) + (1 - omega)(df_i - w_i drho - E_i(u)).
+// Every load of the node (map, gathers, pseudo-potential) is issued before
+// any branch on the map. Links are walked per lane over the set bits of the
+// node's link mask, so a wave iterates as often as its busiest lane has links.
+// A solid node writes zeros into the slots that no link fills, so together
+// with the reflections every slot of the output is written.
 // ---------------------------------------------------------------------------
 template <typename real, int NC, bool SOLIDS>
-__global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
-  const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+__device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, uint32_t y,
+                                             uint32_t z, int& pid, double lv[7]) {
   const uint32_t N = a.N;
-  bool fluid = n < N;
-  if (SOLIDS && fluid) fluid = a.owner[n] == 0;
-  int pid = -1;
-  double lv[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (fluid) {
-    uint32_t x, y, z;
-    node_xyz(n, a.nx, a.ny, x, y, z);
-    Nbr nb(x, y, z, a.nx, a.ny, a.nz);
-    const real* __restrict__ fin = static_cast<const real*>(a.fin);
-    real* __restrict__ fout = static_cast<real*>(a.fout);
-    const real* __restrict__ psi = static_cast<const real*>(a.psi);
+  const uint32_t n = x + a.nx * (y + a.ny * z);
+  Nbr nb(x, y, z, a.nx, a.ny, a.nz);
+  const real* __restrict__ fin = static_cast<const real*>(a.fin);
+  real* __restrict__ fout = static_cast<real*>(a.fout);
+  const real* __restrict__ psi = static_cast<const real*>(a.psi);
 
-    real f[NC][Q];
+  uint32_t lmask = 0;
+  bool fluid = true;
+  if (SOLIDS) {
+    fluid = a.owner[n] == 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      if (a.owner[nb.push(i)] != 0) lmask |= 1u << i;
+  }
+  real f[NC][Q];
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[k][i] = fin[(size_t(k) * Q + i) * N + nb.pull(i)];
+
+  // Shan-Chen acceleration a_k = -G s sum_i w_i psi_kbar(n + c_i) c_i + g; the
+  // rho0 part of psi cancels because every neighbour of a fluid node is fluid
+  // or a frontier solid carrying a virtual density.
+  real ax[NC], ay[NC], az[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    ax[k] = real(a.g[0]);
+    ay[k] = real(a.g[1]);
+    az[k] = real(a.g[2]);
+  }
+  if (NC == 2) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const real* pk = psi + size_t(NC - 1 - k) * N;
+      real sx = 0, sy = 0, sz = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        if (OPP[i] < i) continue;
+        // w_i (psi(n + c_i) - psi(n - c_i)) c_i over pairs of opposite directions
+        const real p = (pk[nb.push(i)] - pk[nb.pull(i)]) * real(WQ[i]);
+        if (CX[i]) sx += CX[i] > 0 ? p : -p;
+        if (CY[i]) sy += CY[i] > 0 ? p : -p;
+        if (CZ[i]) sz += CZ[i] > 0 ? p : -p;
+      }
+      const real gs = real(a.Gs);
+      ax[k] -= gs * sx;
+      ay[k] -= gs * sy;
+      az[k] -= gs * sz;
+    }
+  }
+
+  if (!fluid) {
+    fout[n] = real(0);
 #pragma unroll
     for (int k = 0; k < NC; ++k)
 #pragma unroll
-      for (int i = 0; i < Q; ++i) f[k][i] = fin[(size_t(k) * Q + i) * N + nb.pull(i)];
+      for (int i = 0; i < Q; ++i)
+        if (i == 0 || (lmask & (1u << i))) fout[(size_t(k) * Q + i) * N + n] = real(0);
+    return;
+  }
 
-    real drho[NC], rho[NC], jx[NC], jy[NC], jz[NC];
+  real drho[NC], rho[NC], jx[NC], jy[NC], jz[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      // momentum from differences of opposite populations: f_i and f_opp(i)
-      // are close, so the differences (and their sums) carry few rounding errors
-      real s = f[k][0], sx = 0, sy = 0, sz = 0;
+  for (int k = 0; k < NC; ++k) {
+    // momentum from differences of opposite populations: f_i and f_opp(i)
+    // are close, so the differences (and their sums) carry few rounding errors
+    real s = f[k][0], sx = 0, sy = 0, sz = 0;
 #pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        s += f[k][i];
-        if (OPP[i] < i) continue;
-        const real d = f[k][i] - f[k][OPP[i]];
-        if (CX[i]) sx += CX[i] > 0 ? d : -d;
-        if (CY[i]) sy += CY[i] > 0 ? d : -d;
-        if (CZ[i]) sz += CZ[i] > 0 ? d : -d;
-      }
-      drho[k] = s;
-      rho[k] = real(a.rho0[k]) + s;
-      jx[k] = sx;
-      jy[k] = sy;
-      jz[k] = sz;
+    for (int i = 1; i < Q; ++i) {
+      s += f[k][i];
+      if (OPP[i] < i) continue;
+      const real d = f[k][i] - f[k][OPP[i]];
+      if (CX[i]) sx += CX[i] > 0 ? d : -d;
+      if (CY[i]) sy += CY[i] > 0 ? d : -d;
+      if (CZ[i]) sz += CZ[i] > 0 ? d : -d;
     }
-    real ux, uy, uz;
-    if (NC == 1) {
-      const real ir = real(1) / rho[0];
-      ux = jx[0] * ir;
-      uy = jy[0] * ir;
-      uz = jz[0] * ir;
+    drho[k] = s;
+    rho[k] = real(a.rho0[k]) + s;
+    jx[k] = sx;
+    jy[k] = sy;
+    jz[k] = sz;
+  }
+  real ux, uy, uz;
+  if (NC == 1) {
+    const real ir = real(1) / rho[0];
+    ux = jx[0] * ir;
+    uy = jy[0] * ir;
+    uz = jz[0] * ir;
+  } else {
+    const real t0 = real(a.inv_tau[0]), t1 = real(a.inv_tau[NC - 1]);
+    const real id = real(1) / (rho[0] * t0 + rho[NC - 1] * t1);
+    ux = (jx[0] * t0 + jx[NC - 1] * t1) * id;
+    uy = (jy[0] * t0 + jy[NC - 1] * t1) * id;
+    uz = (jz[0] * t0 + jz[NC - 1] * t1) * id;
+  }
+  real om;
+  if (NC == 1 || a.equal_tau) {
+    om = real(a.omega);
+  } else {
+    // mixture viscosity 1/nu_bar = sum_k (rho_k/rho)/nu_k; omega = 2 cs2/(2 nu_bar + cs2)
+    const real rt = rho[0] + rho[NC - 1];
+    const real inv_nu = (rho[0] / real(a.nu[0]) + rho[NC - 1] / real(a.nu[NC - 1])) / rt;
+    const real nub = real(1) / inv_nu;
+    om = real(2.0 / 3.0) / (real(2) * nub + real(1.0 / 3.0));
+  }
+  const real omc = real(1) - om;
+  const real uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const real vx = ux + ax[k], vy = uy + ay[k], vz = uz + az[k];
+    const real vv = vx * vx + vy * vy + vz * vz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const real w = real(WQ[i]);
+      const real cu = real(CX[i]) * ux + real(CY[i]) * uy + real(CZ[i]) * uz;
+      const real cv = real(CX[i]) * vx + real(CY[i]) * vy + real(CZ[i]) * vz;
+      const real wr = w * rho[k];
+      const real eu = wr * (real(3) * cu + real(4.5) * cu * cu - real(1.5) * uu);
+      const real ev = wr * (real(3) * cv + real(4.5) * cv * cv - real(1.5) * vv);
+      const real wd = w * drho[k];
+      fout[(size_t(k) * Q + i) * N + n] = wd + ev + omc * (f[k][i] - wd - eu);
+    }
+  }
+  if (!SOLIDS) return;
+  const double rho0sum = a.rho0[0] + (NC == 2 ? a.rho0[NC - 1] : 0.0);
+  while (lmask) {
+    const int i = __ffs(lmask) - 1;
+    lmask &= lmask - 1u;
+    const int cx = dir_c(PCX, i), cy = dir_c(PCY, i), cz = dir_c(PCZ, i);
+    const int j = dir_opp(i);
+    const uint32_t s = nbr_dyn(x, y, z, cx, cy, cz, a.nx, a.ny, a.nz);
+    const uint16_t o = a.owner[s];
+    const double wi = (cx * cx + cy * cy + cz * cz == 1) ? W1 : W2;
+    double uwx, uwy, uwz, rwx = 0, rwy = 0, rwz = 0;
+    int p = -1;
+    if (o == OWN_WALL) {
+      const bool lo = int(z) + cz == 0;
+      uwx = lo ? a.wall_lo[0] : a.wall_hi[0];
+      uwy = lo ? a.wall_lo[1] : a.wall_hi[1];
+      uwz = lo ? a.wall_lo[2] : a.wall_hi[2];
     } else {
-      const real t0 = real(a.inv_tau[0]), t1 = real(a.inv_tau[NC - 1]);
-      const real id = real(1) / (rho[0] * t0 + rho[NC - 1] * t1);
-      ux = (jx[0] * t0 + jx[NC - 1] * t1) * id;
-      uy = (jy[0] * t0 + jy[NC - 1] * t1) * id;
-      uz = (jz[0] * t0 + jz[NC - 1] * t1) * id;
+      p = int(o) - 1;
+      const double* P = a.ps + size_t(p) * PSTRIDE;
+      double d;
+      d = double(x) + 0.5 * cx - P[PS_X];
+      rwx = d - a.L[0] * rint(d * a.invL[0]);
+      d = double(y) + 0.5 * cy - P[PS_X + 1];
+      rwy = d - a.L[1] * rint(d * a.invL[1]);
+      d = double(z) + 0.5 * cz - P[PS_X + 2];
+      rwz = d - a.L[2] * rint(d * a.invL[2]);
+      const double wx = P[PS_W], wy = P[PS_W + 1], wz = P[PS_W + 2];
+      uwx = P[PS_V] + (wy * rwz - wz * rwy);
+      uwy = P[PS_V + 1] + (wz * rwx - wx * rwz);
+      uwz = P[PS_V + 2] + (wx * rwy - wy * rwx);
     }
-    real ax[NC], ay[NC], az[NC];
+    const real cw = real(6.0 * wi * (uwx * cx + uwy * cy + uwz * cz));
+    double dev = 0.0;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      ax[k] = real(a.g[0]);
-      ay[k] = real(a.g[1]);
-      az[k] = real(a.g[2]);
+      // the post-collision value this thread has just stored
+      const real fs = fout[(size_t(k) * Q + i) * N + n];
+      const real corr = cw * rho[k];
+      fout[(size_t(k) * Q + j) * N + s] = fs - corr;
+      dev += double(real(2) * fs - corr);
     }
-    if (NC == 2) {
-      // sum_i w_i psi(n + c_i) c_i; the rho0 part cancels because every
-      // neighbour of a fluid node is fluid or a frontier solid with psi.
+    if (p < 0) continue;
+    const double fl = 2.0 * wi * rho0sum + dev;  // F_link = fl c_i
+    const double Fx = fl * cx, Fy = fl * cy, Fz = fl * cz;
+    if (p != pid) {
+      if (pid >= 0) {  // this thread's links touch another sphere: flush the first one
+        double* acp = a.acc + size_t(pid) * ASTRIDE;
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const real* pk = psi + size_t(NC - 1 - k) * N;
-        real sx = 0, sy = 0, sz = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          if (OPP[i] < i) continue;
-          // w_i (psi(n + c_i) - psi(n - c_i)) c_i over pairs of opposite directions
-          const real p = (pk[nb.push(i)] - pk[nb.pull(i)]) * real(WQ[i]);
-          if (CX[i]) sx += CX[i] > 0 ? p : -p;
-          if (CY[i]) sy += CY[i] > 0 ? p : -p;
-          if (CZ[i]) sz += CZ[i] > 0 ? p : -p;
-        }
-        const real gs = real(a.Gs);
-        ax[k] -= gs * sx;
-        ay[k] -= gs * sy;
-        az[k] -= gs * sz;
+        for (int c = 0; c < 6; ++c) unsafeAtomicAdd(acp + AC_FLIQ + c, lv[c]);
+        unsafeAtomicAdd(acp + AC_FLABS, lv[6]);
       }
-    }
-    real om;
-    if (NC == 1 || a.equal_tau) {
-      om = real(a.omega);
-    } else {
-      // mixture viscosity 1/nu_bar = sum_k (rho_k/rho)/nu_k; omega = 2 cs2/(2 nu_bar + cs2)
-      const real rt = rho[0] + rho[NC - 1];
-      const real inv_nu = (rho[0] / real(a.nu[0]) + rho[NC - 1] / real(a.nu[NC - 1])) / rt;
-      const real nub = real(1) / inv_nu;
-      om = real(2.0 / 3.0) / (real(2) * nub + real(1.0 / 3.0));
-    }
-    const real omc = real(1) - om;
-    const real uu = ux * ux + uy * uy + uz * uz;
+      pid = p;
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const real vx = ux + ax[k], vy = uy + ay[k], vz = uz + az[k];
-      const real vv = vx * vx + vy * vy + vz * vz;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const real w = real(WQ[i]);
-        const real cu = real(CX[i]) * ux + real(CY[i]) * uy + real(CZ[i]) * uz;
-        const real cv = real(CX[i]) * vx + real(CY[i]) * vy + real(CZ[i]) * vz;
-        const real wr = w * rho[k];
-        const real eu = wr * (real(3) * cu + real(4.5) * cu * cu - real(1.5) * uu);
-        const real ev = wr * (real(3) * cv + real(4.5) * cv * cv - real(1.5) * vv);
-        const real wd = w * drho[k];
-        const real fs = wd + ev + omc * (f[k][i] - wd - eu);
-        f[k][i] = fs;
-        fout[(size_t(k) * Q + i) * N + n] = fs;
+      for (int c = 0; c < 7; ++c) lv[c] = 0.0;
+    }
+    lv[0] += Fx;
+    lv[1] += Fy;
+    lv[2] += Fz;
+    lv[3] += rwy * Fz - rwz * Fy;
+    lv[4] += rwz * Fx - rwx * Fz;
+    lv[5] += rwx * Fy - rwy * Fx;
+    lv[6] += fabs(fl) * (wi == W1 ? 1.0 : 1.4142135623730951);
+  }
+}
+
+// One workgroup updates a TX x TY tile of x-y rows for TZ consecutive z
+// planes, so the pseudo-potential planes it reads are reused from cache by
+// the same workgroup. Tiles are dealt out so that each of the 8 XCDs (which
+// take workgroups round-robin) works on one contiguous slab of tiles and
+// the tiles sharing stencil halos share its L2.
+constexpr int TX = 64, TY = BLOCK / TX, TZ = 8;
+
+template <typename real, int NC, bool SOLIDS>
+__global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
+  const uint32_t bid = blockIdx.x;
+  const uint32_t t = (bid % 8u) * a.tiles_per_xcd + bid / 8u;
+  int pid = -1;
+  double lv[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (t < a.tiles) {
+    const uint32_t tx = t % a.ntx, r = t / a.ntx, ty = r % a.nty, tz = r / a.nty;
+    const uint32_t x = tx * TX + threadIdx.x % TX, y = ty * TY + threadIdx.x / TX;
+    if (x < a.nx && y < a.ny)
+      for (int zz = 0; zz < TZ; ++zz) {
+        const uint32_t z = tz * TZ + zz;
+        if (z < a.nz) collide_node<real, NC, SOLIDS>(a, x, y, z, pid, lv);
       }
-    }
-    if (SOLIDS) {
-      const double rho0sum = a.rho0[0] + (NC == 2 ? a.rho0[1] : 0.0);
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const uint32_t s = nb.push(i);
-        const uint16_t o = a.owner[s];
-        if (o == 0) continue;
-        double uwx, uwy, uwz, rwx = 0, rwy = 0, rwz = 0;
-        int p = -1;
-        if (o == OWN_WALL) {
-          const double* U = (int(z) + CZ[i] == 0) ? a.wall_lo : a.wall_hi;
-          uwx = U[0];
-          uwy = U[1];
-          uwz = U[2];
-        } else {
-          p = int(o) - 1;
-          const double* P = a.ps + size_t(p) * PSTRIDE;
-          rwx = min_image(double(x) + 0.5 * CX[i] - P[PS_X], a.L[0]);
-          rwy = min_image(double(y) + 0.5 * CY[i] - P[PS_X + 1], a.L[1]);
-          rwz = min_image(double(z) + 0.5 * CZ[i] - P[PS_X + 2], a.L[2]);
-          const double wx = P[PS_W], wy = P[PS_W + 1], wz = P[PS_W + 2];
-          uwx = P[PS_V] + (wy * rwz - wz * rwy);
-          uwy = P[PS_V + 1] + (wz * rwx - wx * rwz);
-          uwz = P[PS_V + 2] + (wx * rwy - wy * rwx);
-        }
-        const double cuw = uwx * CX[i] + uwy * CY[i] + uwz * CZ[i];
-        const real cw = real(6.0 * WQ[i] * cuw);
-        double dev = 0.0;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-          const real corr = cw * rho[k];
-          fout[(size_t(k) * Q + OPP[i]) * N + s] = f[k][i] - corr;
-          dev += double(real(2) * f[k][i] - corr);
-        }
-        if (p >= 0) {
-          const double fl = 2.0 * WQ[i] * rho0sum + dev;  // F_link = fl * c_i
-          const double Fx = fl * CX[i], Fy = fl * CY[i], Fz = fl * CZ[i];
-          if (p != pid) {
-            if (pid >= 0) {  // a node touching two spheres: flush the first one
-              double* acp = a.acc + size_t(pid) * ASTRIDE;
-              for (int c = 0; c < 6; ++c) unsafeAtomicAdd(acp + AC_FLIQ + c, lv[c]);
-              unsafeAtomicAdd(acp + AC_FLABS, lv[6]);
-            }
-            pid = p;
-            for (int c = 0; c < 7; ++c) lv[c] = 0.0;
-          }
-          lv[0] += Fx;
-          lv[1] += Fy;
-          lv[2] += Fz;
-          lv[3] += rwy * Fz - rwz * Fy;
-          lv[4] += rwz * Fx - rwx * Fz;
-          lv[5] += rwx * Fy - rwy * Fx;
-          lv[6] += fabs(fl) * ((CX[i] && CY[i]) || (CX[i] && CZ[i]) || (CY[i] && CZ[i])
-                                   ? 1.4142135623730951
-                                   : 1.0);
-        }
-      }
-    }
   }
   if (SOLIDS && a.acc) flush_links(a.acc, pid, lv);
 }
@@ -575,7 +635,7 @@ hipError_t launch_density(lb_ctx* c, const void* f) {
 
 template <typename real, int NC>
 static void collide_t(lb_ctx* c, const CollideArgs& a) {
-  dim3 grid(nblocks(c->geo.N));
+  dim3 grid(8u * a.tiles_per_xcd);
   if (c->has_solids)
     hipLaunchKernelGGL((k_collide<real, NC, true>), grid, dim3(BLOCK), 0, c->stream, a);
   else
@@ -605,6 +665,11 @@ hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t
   a.L[0] = g.nx;
   a.L[1] = g.ny;
   a.L[2] = g.nz;
+  for (int d = 0; d < 3; ++d) a.invL[d] = 1.0 / a.L[d];
+  a.ntx = (g.nx + TX - 1) / TX;
+  a.nty = (g.ny + TY - 1) / TY;
+  a.tiles = a.ntx * a.nty * ((g.nz + TZ - 1) / TZ);
+  a.tiles_per_xcd = (a.tiles + 7) / 8;
   const int kb = g.ncomp == 2 ? 1 : 0;
   a.rho0[0] = P.rho0[0];
   a.rho0[1] = P.rho0[kb];

@@ -73,8 +73,8 @@ struct lb_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
-  double phase_ms[LB_NPHASE] = {0, 0, 0, 0, 0};
-  int64_t phase_n[LB_NPHASE] = {0, 0, 0, 0, 0};
+  double phase_ms[LB_NPHASE] = {};
+  int64_t phase_n[LB_NPHASE] = {};
   std::string err;
 };
 

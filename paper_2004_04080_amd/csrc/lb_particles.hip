@@ -275,50 +275,58 @@ __global__ void __launch_bounds__(PBLOCK) k_fill_sphere(PArgs a) {
   const uint32_t N = a.N;
   double v[6] = {0, 0, 0, 0, 0, 0};
   for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
-    int x, y, z;
-    box_node(b, t, x, y, z);
-    const uint32_t wx = wrap_int(x, a.nx), wy = wrap_int(y, a.ny), wz = wrap_int(z, a.nz);
-    const uint32_t n = wx + a.nx * (wy + a.ny * wz);
-    if (a.own_new[n] != me) continue;
-    Nbr nb(wx, wy, wz, a.nx, a.ny, a.nz);
-    double wsum = 0.0, s[2] = {0, 0}, Ws[3] = {0, 0, 0}, g[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    for (int i = 1; i < Q; ++i) {
-      const uint32_t m = nb.push(i);
-      if (a.own_new[m] != 0) continue;
-      wsum += WQ[i];
-      Ws[0] += WQ[i] * CX[i];
-      Ws[1] += WQ[i] * CY[i];
-      Ws[2] += WQ[i] * CZ[i];
-      for (int k = 0; k < a.ncomp; ++k) {
-        const double dp = double(psi[size_t(k) * N + m]);
-        s[k] += WQ[i] * dp;
-        g[k][0] += WQ[i] * dp * CX[i];
-        g[k][1] += WQ[i] * dp * CY[i];
-        g[k][2] += WQ[i] * dp * CZ[i];
+    uint32_t n = 0, mask = 0;
+    {
+      int x, y, z;
+      box_node(b, t, x, y, z);
+      const uint32_t wx = wrap_int(x, a.nx), wy = wrap_int(y, a.ny), wz = wrap_int(z, a.nz);
+      n = wx + a.nx * (wy + a.ny * wz);
+      if (a.own_new[n] == me) {
+        Nbr nb(wx, wy, wz, a.nx, a.ny, a.nz);
+#pragma unroll
+        for (int i = 1; i < Q; ++i)
+          if (a.own_new[nb.push(i)] == 0) mask |= 1u << i;
+        double wsum = 0.0, s[2] = {0, 0}, Ws[3] = {0, 0, 0}, g[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        for (int i = 1; i < Q; ++i) {
+          if (!(mask & (1u << i))) continue;
+          const uint32_t m = nb.push(i);
+          wsum += WQ[i];
+          Ws[0] += WQ[i] * CX[i];
+          Ws[1] += WQ[i] * CY[i];
+          Ws[2] += WQ[i] * CZ[i];
+          for (int k = 0; k < a.ncomp; ++k) {
+            const double dp = double(psi[size_t(k) * N + m]);
+            s[k] += WQ[i] * dp;
+            g[k][0] += WQ[i] * dp * CX[i];
+            g[k][1] += WQ[i] * dp * CY[i];
+            g[k][2] += WQ[i] * dp * CZ[i];
+          }
+        }
+        if (mask) {
+          double dv[2];
+          for (int k = 0; k < a.ncomp; ++k) {
+            dv[k] = a.zeta[k] * a.rho0[k] + (1.0 + a.zeta[k]) * s[k] / wsum;
+            psi[size_t(k) * N + n] = real(dv[k]);
+          }
+          if (a.ncomp == 2) {
+            double F[3] = {0, 0, 0};
+            for (int k = 0; k < 2; ++k) {
+              const int kb = 1 - k;
+              const double pk = a.rho0[k] + dv[k];
+              for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + g[kb][c]);
+            }
+            const double d[3] = {min_image(double(wx) - xc[0], a.L[0]),
+                                 min_image(double(wy) - xc[1], a.L[1]),
+                                 min_image(double(wz) - xc[2], a.L[2])};
+            v[0] += F[0];
+            v[1] += F[1];
+            v[2] += F[2];
+            v[3] += d[1] * F[2] - d[2] * F[1];
+            v[4] += d[2] * F[0] - d[0] * F[2];
+            v[5] += d[0] * F[1] - d[1] * F[0];
+          }
+        }
       }
-    }
-    if (wsum == 0.0) continue;
-    double dv[2];
-    for (int k = 0; k < a.ncomp; ++k) {
-      dv[k] = a.zeta[k] * a.rho0[k] + (1.0 + a.zeta[k]) * s[k] / wsum;
-      psi[size_t(k) * N + n] = real(dv[k]);
-    }
-    if (a.ncomp == 2) {
-      double F[3] = {0, 0, 0};
-      for (int k = 0; k < 2; ++k) {
-        const int kb = 1 - k;
-        const double pk = a.rho0[k] + dv[k];
-        for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + g[kb][c]);
-      }
-      const double d[3] = {min_image(double(wx) - xc[0], a.L[0]),
-                           min_image(double(wy) - xc[1], a.L[1]),
-                           min_image(double(wz) - xc[2], a.L[2])};
-      v[0] += F[0];
-      v[1] += F[1];
-      v[2] += F[2];
-      v[3] += d[1] * F[2] - d[2] * F[1];
-      v[4] += d[2] * F[0] - d[0] * F[2];
-      v[5] += d[0] * F[1] - d[1] * F[0];
     }
   }
   block_sum<6>(v);
@@ -629,7 +637,7 @@ hipError_t launch_step_particles_pre(lb_ctx* c) {
 
 hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces) {
   PArgs a = pargs(c, const_cast<uint16_t*>(owner), owner);
-  if (!forces) a.acc = nullptr;
+  if (!forces) a.acc = nullptr;  // psi only: leave the force terms alone
   if (c->geo.prec == LB_FP64)
     hipLaunchKernelGGL(k_fill_sphere<double>, dim3(c->nparticles), dim3(PBLOCK), 0, c->stream, a);
   else

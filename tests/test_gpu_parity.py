@@ -17,17 +17,22 @@ pytestmark = [pytest.mark.gpu, requires_gpu]
 
 TOL64 = 1e-12
 TOL32 = 1e-5
+# FP32 velocity: u = sum_i f_i c_i / rho from 19 stored deviations of up to
+# ~0.95 w_i once the phases separate; FP32 storage leaves ~5e-8 absolute
+# error per population, i.e. |du| ~ 1e-7, which is ~2e-5 of max|u| ~ 5e-3.
+TOL32_U = 5e-5
 
 
-def _check(o, lat, tol, what="", df_gate=True):
-    """Gate every field at tol; df (deviations) only when df_gate (short horizons)."""
+def _check(o, lat, tol, what="", df_gate=True, tol_u=None):
+    """Gate every field at tol (u at tol_u when given); df (deviations) only
+    when df_gate (short horizons)."""
     e = compare(o, lat)
     print(what, {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in e.items()}, flush=True)
     assert e.pop("owner_equal")
     if not df_gate:
         e.pop("df")
     for k, v in e.items():
-        assert v <= tol, (what, k, v)
+        assert v <= (tol_u if (k == "u" and tol_u is not None) else tol), (what, k, v)
     return e
 
 
@@ -76,13 +81,13 @@ def test_two_fluids_fp32_step_and_trajectory():
     # trajectory from the common initial state
     o.step(10)
     lat.step(10)
-    _check(o, lat, TOL32, "fp32 trajectory t=10")
+    _check(o, lat, TOL32, "fp32 trajectory t=10", tol_u=TOL32_U)
     # step parity from a state both hold exactly
     lat.step(190)
     sync_state(o, lat)
     o.step(1)
     lat.step(1)
-    _check(o, lat, TOL32, "fp32 step t=201")
+    _check(o, lat, TOL32, "fp32 step t=201", tol_u=TOL32_U)
 
 
 def test_walls_moving_fp64():
@@ -141,7 +146,7 @@ def test_moving_spheres_fp32_step_parity():
     for t in range(3):
         o.step(1)
         lat.step(1)
-        _check(o, lat, TOL32, f"fp32 spheres step {t}")
+        _check(o, lat, TOL32, f"fp32 spheres step {t}", tol_u=TOL32_U)
         ep = compare_particles(o, lat)
         print("particles", {k: f"{v:.1e}" for k, v in ep.items()}, flush=True)
         for k in ("Fliq", "Tliq", "FSC", "TSC", "Fd", "Fc"):
