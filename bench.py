@@ -14,6 +14,7 @@ oracle's MLUPS on a bounded sample of the workload (CPU baseline).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -93,7 +94,32 @@ def run_gpu(w, rho, x, precision, steps, warmup, want_roofline):
     return out
 
 
-def roofline(w, res, es):
+COUNTERS = os.path.join(ROOT, "profiles", "k_collide_T512_fp32_hbm_counters.md")
+COLLIDE_SOURCES = ("paper_2004_04080_amd/csrc/lb_fluid.hip", "paper_2004_04080_amd/csrc/lb_device.hpp")
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per collide launch from the committed rocprofv3 FETCH_SIZE and
+    WRITE_SIZE counters (scaled by the copy calibration), or None when they were
+    taken on another workload or the collide sources changed since."""
+    if workload != "T" or precision != "fp32":
+        return None
+    try:
+        text = open(COUNTERS).read()
+        block = text.split("```counters", 1)[1].split("```", 1)[0]
+        kv = dict(line.split(": ", 1) for line in block.strip().splitlines())
+        h = hashlib.sha256()
+        for f in COLLIDE_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv["source_sha256"]:
+            return None
+        return int(float(kv["traffic_bytes_per_dispatch"]))
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
+def roofline(w, res, es, precision):
     """Algorithmic bytes of one collide launch over its average duration."""
     K = w.ncomp
     nfl, nlinks, N = res["fluid_nodes"], res["links"], w.N
@@ -104,7 +130,8 @@ def roofline(w, res, es):
     avg_ms = ms / max(n, 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(w.name, precision),
             "kernel": "k_collide", "bytes_per_launch": bytes_launch,
             "avg_launch_ms": round(avg_ms, 4)}
 
@@ -203,7 +230,7 @@ def main():
                                f"(tau=1, G=0.65) + {w.nparticles} moving spheres R={w.radius}",
                    "nodes": w.N, "spheres": w.nparticles,
                    "fluid_nodes": res["fluid_nodes"], "links": res["links"]},
-        "roofline": roofline(w, res, es),
+        "roofline": roofline(w, res, es, args.precision),
         "cpu_baseline": cpu,
         "fp64": fp64,
         "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)

@@ -63,6 +63,11 @@ int validate(const lb_params* p, std::string& why) {
       return LB_E_ARG;
     }
   if (p->precision != LB_FP32 && p->precision != LB_FP64) { why = "bad precision"; return LB_E_ARG; }
+  // kernels address one population plane [k][i][*] with 32-bit byte offsets
+  if (N * (p->precision == LB_FP64 ? 8u : 4u) > 0xFFFFFFFFull) {
+    why = "one population plane (nodes x element size) exceeds 4 GiB";
+    return LB_E_SHAPE;
+  }
   if (p->max_particles < 0 || p->max_particles > 65534) {
     why = "max_particles must be in [0, 65534]";
     return LB_E_ARG;

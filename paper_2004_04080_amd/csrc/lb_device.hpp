@@ -80,6 +80,34 @@ __device__ __forceinline__ uint32_t nbr_dyn(uint32_t x, uint32_t y, uint32_t z, 
   return uint32_t(a) + nx * (uint32_t(b) + ny * uint32_t(c));
 }
 
+// Element access base[idx] with a 32-bit index off a wave-uniform base. The
+// byte offset stays 32-bit, so the access takes the scalar-base plus
+// vector-offset address form with no 64-bit address arithmetic per lane.
+// Callers keep every array addressed this way below 4 GiB per base.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     idx * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, uint32_t idx, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T))) = v;
+}
+
+// c_i . (x, y, z) for a direction known at compile time, from sign flips and
+// adds only (a multiply by a zero component would not fold away in IEEE mode)
+template <typename real>
+__device__ __forceinline__ real cdot(int i, real x, real y, real z) {
+  real s = real(0);
+  bool have = false;
+  if (CX[i]) { s = CX[i] > 0 ? x : -x; have = true; }
+  if (CY[i]) { const real t = CY[i] > 0 ? y : -y; s = have ? s + t : t; have = true; }
+  if (CZ[i]) { const real t = CZ[i] > 0 ? z : -z; s = have ? s + t : t; }
+  return s;
+}
+// |c_i|^2 == 1: the direction has weight 1/18 (else 1/36, or 1/3 at rest)
+constexpr bool axis_dir(int i) { return CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i] == 1; }
+
 __device__ __forceinline__ void node_xyz(uint32_t n, uint32_t nx, uint32_t ny, uint32_t& x,
                                          uint32_t& y, uint32_t& z) {
   x = n % nx;

@@ -92,7 +92,7 @@ struct CollideArgs {
   int equal_tau;
   double wall_lo[3], wall_hi[3];
   double L[3], invL[3];
-  uint32_t ntx, nty, tiles, tiles_per_xcd;  // tiling of the collide grid
+  uint32_t blocks_per_xcd;  // workgroups per XCD (grid = 8 x blocks_per_xcd)
 };
 
 // Packed direction tables for a direction index that varies per lane:
@@ -143,8 +143,15 @@ __device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, d
 // moving-wall reflection (Eq. bbv, LADDFLBE, UPI) into the slot of that node
 // which this node gathers next step, and the link momentum exchange
 // (Eq. LADDFORCE) summed per sphere (Eq. FORCEPARTEQ, TORQUEPARTEQ).
-// In deviation form with E_i(v) = w_i rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v):
-//   df*_i = w_i drho + E_i(u + a) + (1 - omega)(df_i - w_i drho - E_i(u)).
+//
+// Collision in deviation form, with E_i(v) = w_i rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v):
+//   df*_i = w_i drho + E_i(u + a) + (1 - omega)(df_i - w_i drho - E_i(u)),
+// which regroups, per pair of opposite directions i and -i, into a part even
+// in c_i and a part odd in c_i (o = 1 - omega, v = u + a):
+//   df*_{+-i} = o df_{+-i} + w_i [S + 4.5 rho ((c.v)^2 - o (c.u)^2)]
+//                          +- 3 w_i rho (c.v - o c.u),
+//   S = omega drho - 1.5 rho (v.v - o u.u),
+// so each pair costs one evaluation of the two parts.
 // Every load of the node (map, gathers, pseudo-potential) is issued before
 // any branch on the map. Links are walked per lane over the set bits of the
 // node's link mask, so a wave iterates as often as its busiest lane has links.
@@ -152,10 +159,9 @@ __device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, d
 // with the reflections every slot of the output is written.
 // ---------------------------------------------------------------------------
 template <typename real, int NC, bool SOLIDS>
-__device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, uint32_t y,
-                                             uint32_t z, int& pid, double lv[7]) {
+__device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t n, uint32_t x,
+                                             uint32_t y, uint32_t z, int& pid, double lv[7]) {
   const uint32_t N = a.N;
-  const uint32_t n = x + a.nx * (y + a.ny * z);
   Nbr nb(x, y, z, a.nx, a.ny, a.nz);
   const real* __restrict__ fin = static_cast<const real*>(a.fin);
   real* __restrict__ fout = static_cast<real*>(a.fout);
@@ -164,20 +170,21 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, u
   uint32_t lmask = 0;
   bool fluid = true;
   if (SOLIDS) {
-    fluid = a.owner[n] == 0;
+    fluid = ld32(a.owner, n) == 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i)
-      if (a.owner[nb.push(i)] != 0) lmask |= 1u << i;
+      if (ld32(a.owner, nb.push(i)) != 0) lmask |= 1u << i;
   }
   real f[NC][Q];
 #pragma unroll
   for (int k = 0; k < NC; ++k)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[k][i] = fin[(size_t(k) * Q + i) * N + nb.pull(i)];
+    for (int i = 0; i < Q; ++i) f[k][i] = ld32(fin + (size_t(k) * Q + i) * N, nb.pull(i));
 
   // Shan-Chen acceleration a_k = -G s sum_i w_i psi_kbar(n + c_i) c_i + g; the
   // rho0 part of psi cancels because every neighbour of a fluid node is fluid
-  // or a frontier solid carrying a virtual density.
+  // or a frontier solid carrying a virtual density. Summed over pairs of
+  // opposite directions, axis (w = 1/18) and diagonal (w = 1/36) terms apart.
   real ax[NC], ay[NC], az[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
@@ -189,30 +196,32 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, u
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       const real* pk = psi + size_t(NC - 1 - k) * N;
-      real sx = 0, sy = 0, sz = 0;
+      real s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         if (OPP[i] < i) continue;
-        // w_i (psi(n + c_i) - psi(n - c_i)) c_i over pairs of opposite directions
-        const real p = (pk[nb.push(i)] - pk[nb.pull(i)]) * real(WQ[i]);
-        if (CX[i]) sx += CX[i] > 0 ? p : -p;
-        if (CY[i]) sy += CY[i] > 0 ? p : -p;
-        if (CZ[i]) sz += CZ[i] > 0 ? p : -p;
+        const real p = ld32(pk, nb.push(i)) - ld32(pk, nb.pull(i));
+        const int c[3] = {CX[i], CY[i], CZ[i]};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (!c[d]) continue;
+          if (axis_dir(i)) s1[d] += c[d] > 0 ? p : -p;
+          else s2[d] += c[d] > 0 ? p : -p;
+        }
       }
       const real gs = real(a.Gs);
-      ax[k] -= gs * sx;
-      ay[k] -= gs * sy;
-      az[k] -= gs * sz;
+      ax[k] -= gs * (real(W1) * s1[0] + real(W2) * s2[0]);
+      ay[k] -= gs * (real(W1) * s1[1] + real(W2) * s2[1]);
+      az[k] -= gs * (real(W1) * s1[2] + real(W2) * s2[2]);
     }
   }
 
   if (!fluid) {
-    fout[n] = real(0);
 #pragma unroll
     for (int k = 0; k < NC; ++k)
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        if (i == 0 || (lmask & (1u << i))) fout[(size_t(k) * Q + i) * N + n] = real(0);
+        if (i == 0 || (lmask & (1u << i))) st32(fout + (size_t(k) * Q + i) * N, n, real(0));
     return;
   }
 
@@ -221,21 +230,22 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, u
   for (int k = 0; k < NC; ++k) {
     // momentum from differences of opposite populations: f_i and f_opp(i)
     // are close, so the differences (and their sums) carry few rounding errors
-    real s = f[k][0], sx = 0, sy = 0, sz = 0;
+    real s = f[k][0], j[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       s += f[k][i];
       if (OPP[i] < i) continue;
       const real d = f[k][i] - f[k][OPP[i]];
-      if (CX[i]) sx += CX[i] > 0 ? d : -d;
-      if (CY[i]) sy += CY[i] > 0 ? d : -d;
-      if (CZ[i]) sz += CZ[i] > 0 ? d : -d;
+      const int c[3] = {CX[i], CY[i], CZ[i]};
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+        if (c[e]) j[e] += c[e] > 0 ? d : -d;
     }
     drho[k] = s;
     rho[k] = real(a.rho0[k]) + s;
-    jx[k] = sx;
-    jy[k] = sy;
-    jz[k] = sz;
+    jx[k] = j[0];
+    jy[k] = j[1];
+    jz[k] = j[2];
   }
   real ux, uy, uz;
   if (NC == 1) {
@@ -261,21 +271,35 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, u
     om = real(2.0 / 3.0) / (real(2) * nub + real(1.0 / 3.0));
   }
   const real omc = real(1) - om;
-  const real uu = ux * ux + uy * uy + uz * uz;
+  const real ouu = omc * (ux * ux + uy * uy + uz * uz);
+  // (1 - omega) c.u and (1 - omega)(c.u)^2 per pair, shared by the components
+  real ocu[Q], ocu2[Q];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (OPP[i] < i) continue;
+    const real cu = cdot(i, ux, uy, uz);
+    ocu[i] = omc * cu;
+    ocu2[i] = ocu[i] * cu;
+  }
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     const real vx = ux + ax[k], vy = uy + ay[k], vz = uz + az[k];
-    const real vv = vx * vx + vy * vy + vz * vz;
+    const real S = om * drho[k] - real(1.5) * rho[k] * ((vx * vx + vy * vy + vz * vz) - ouu);
+    const real A = real(4.5) * rho[k], B = real(3) * rho[k];
+    const real wS[2] = {real(W1) * S, real(W2) * S};
+    const real wA[2] = {real(W1) * A, real(W2) * A};
+    const real wB[2] = {real(W1) * B, real(W2) * B};
+    real* fk = fout + size_t(k) * Q * N;
+    st32(fk, n, omc * f[k][0] + real(1.0 / 3.0) * S);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const real w = real(WQ[i]);
-      const real cu = real(CX[i]) * ux + real(CY[i]) * uy + real(CZ[i]) * uz;
-      const real cv = real(CX[i]) * vx + real(CY[i]) * vy + real(CZ[i]) * vz;
-      const real wr = w * rho[k];
-      const real eu = wr * (real(3) * cu + real(4.5) * cu * cu - real(1.5) * uu);
-      const real ev = wr * (real(3) * cv + real(4.5) * cv * cv - real(1.5) * vv);
-      const real wd = w * drho[k];
-      fout[(size_t(k) * Q + i) * N + n] = wd + ev + omc * (f[k][i] - wd - eu);
+    for (int i = 1; i < Q; ++i) {
+      if (OPP[i] < i) continue;
+      const int cls = axis_dir(i) ? 0 : 1;
+      const real cv = cdot(i, vx, vy, vz);
+      const real E = (cv * cv - ocu2[i]) * wA[cls] + wS[cls];
+      const real D = (cv - ocu[i]) * wB[cls];
+      st32(fk + size_t(i) * N, n, omc * f[k][i] + (E + D));
+      st32(fk + size_t(OPP[i]) * N, n, omc * f[k][OPP[i]] + (E - D));
     }
   }
   if (!SOLIDS) return;
@@ -286,7 +310,7 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, u
     const int cx = dir_c(PCX, i), cy = dir_c(PCY, i), cz = dir_c(PCZ, i);
     const int j = dir_opp(i);
     const uint32_t s = nbr_dyn(x, y, z, cx, cy, cz, a.nx, a.ny, a.nz);
-    const uint16_t o = a.owner[s];
+    const uint16_t o = ld32(a.owner, s);
     const double wi = (cx * cx + cy * cy + cz * cz == 1) ? W1 : W2;
     double uwx, uwy, uwz, rwx = 0, rwy = 0, rwz = 0;
     int p = -1;
@@ -315,9 +339,9 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, u
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       // the post-collision value this thread has just stored
-      const real fs = fout[(size_t(k) * Q + i) * N + n];
+      const real fs = ld32(fout + (size_t(k) * Q + i) * N, n);
       const real corr = cw * rho[k];
-      fout[(size_t(k) * Q + j) * N + s] = fs - corr;
+      st32(fout + (size_t(k) * Q + j) * N, s, fs - corr);
       dev += double(real(2) * fs - corr);
     }
     if (p < 0) continue;
@@ -344,27 +368,19 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t x, u
   }
 }
 
-// One workgroup updates a TX x TY tile of x-y rows for TZ consecutive z
-// planes, so the pseudo-potential planes it reads are reused from cache by
-// the same workgroup. Tiles are dealt out so that each of the 8 XCDs (which
-// take workgroups round-robin) works on one contiguous slab of tiles and
-// the tiles sharing stencil halos share its L2.
-constexpr int TX = 64, TY = BLOCK / TX, TZ = 8;
-
+// One thread per node, in node order. Workgroups are dealt round-robin over
+// the 8 XCDs; the block index is remapped so that each XCD sweeps one
+// contiguous range of nodes and neighbouring rows share that XCD's L2.
 template <typename real, int NC, bool SOLIDS>
 __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
-  const uint32_t bid = blockIdx.x;
-  const uint32_t t = (bid % 8u) * a.tiles_per_xcd + bid / 8u;
+  const uint32_t b = (blockIdx.x % 8u) * a.blocks_per_xcd + blockIdx.x / 8u;
+  const uint32_t n = b * BLOCK + threadIdx.x;
   int pid = -1;
   double lv[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (t < a.tiles) {
-    const uint32_t tx = t % a.ntx, r = t / a.ntx, ty = r % a.nty, tz = r / a.nty;
-    const uint32_t x = tx * TX + threadIdx.x % TX, y = ty * TY + threadIdx.x / TX;
-    if (x < a.nx && y < a.ny)
-      for (int zz = 0; zz < TZ; ++zz) {
-        const uint32_t z = tz * TZ + zz;
-        if (z < a.nz) collide_node<real, NC, SOLIDS>(a, x, y, z, pid, lv);
-      }
+  if (n < a.N) {
+    uint32_t x, y, z;
+    node_xyz(n, a.nx, a.ny, x, y, z);
+    collide_node<real, NC, SOLIDS>(a, n, x, y, z, pid, lv);
   }
   if (SOLIDS && a.acc) flush_links(a.acc, pid, lv);
 }
@@ -635,7 +651,7 @@ hipError_t launch_density(lb_ctx* c, const void* f) {
 
 template <typename real, int NC>
 static void collide_t(lb_ctx* c, const CollideArgs& a) {
-  dim3 grid(8u * a.tiles_per_xcd);
+  dim3 grid(8u * a.blocks_per_xcd);
   if (c->has_solids)
     hipLaunchKernelGGL((k_collide<real, NC, true>), grid, dim3(BLOCK), 0, c->stream, a);
   else
@@ -666,10 +682,7 @@ hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t
   a.L[1] = g.ny;
   a.L[2] = g.nz;
   for (int d = 0; d < 3; ++d) a.invL[d] = 1.0 / a.L[d];
-  a.ntx = (g.nx + TX - 1) / TX;
-  a.nty = (g.ny + TY - 1) / TY;
-  a.tiles = a.ntx * a.nty * ((g.nz + TZ - 1) / TZ);
-  a.tiles_per_xcd = (a.tiles + 7) / 8;
+  a.blocks_per_xcd = (nblocks(g.N) + 7) / 8;
   const int kb = g.ncomp == 2 ? 1 : 0;
   a.rho0[0] = P.rho0[0];
   a.rho0[1] = P.rho0[kb];

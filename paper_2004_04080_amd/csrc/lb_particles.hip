@@ -166,10 +166,16 @@ __global__ void __launch_bounds__(PBLOCK) k_events(PArgs a) {
     lo[d] = fmin(xc[d], xo[d]);
     hi[d] = fmax(xc[d], xo[d]);
   }
+  // A sphere within the speed limit moves at most 1/2 per axis and step; a
+  // larger (or non-finite) displacement raises the speed flag and skips the
+  // events, which keeps the box (and the kernel's run time) bounded.
+  bool jump = false;
+  for (int d = 0; d < 3; ++d) jump = jump || !(hi[d] - lo[d] <= 1.0);
+  if (jump && threadIdx.x == 0) atomicOr(a.flags, 1);
   Box b;
   b.total = 1;
   for (int d = 0; d < 3; ++d) {
-    if (!isfinite(lo[d]) || !isfinite(hi[d]) || fabs(lo[d]) > 1e7 || fabs(hi[d]) > 1e7) {
+    if (jump || !isfinite(lo[d]) || !isfinite(hi[d]) || fabs(lo[d]) > 1e7 || fabs(hi[d]) > 1e7) {
       b.total = 0;
       b.lo[d] = 0;
       b.n[d] = 0;
@@ -354,12 +360,18 @@ struct CellArgs {
   double zlo, zhi;
 };
 
+// cell of one coordinate, clamped to [0, nc) in floating point before the
+// conversion (a non-finite coordinate lands in cell 0)
+__device__ __forceinline__ int cell_index(double x, double cs, int nc) {
+  double q = floor(x / cs);
+  q = q >= 0.0 ? q : 0.0;
+  q = q <= double(nc - 1) ? q : double(nc - 1);
+  return int(q);
+}
+
 __device__ __forceinline__ int cell_of(const CellArgs& a, const double* x) {
   int ci[3];
-  for (int d = 0; d < 3; ++d) {
-    int c = int(floor(x[d] / a.cs[d]));
-    ci[d] = c < 0 ? 0 : (c >= a.nc[d] ? a.nc[d] - 1 : c);
-  }
+  for (int d = 0; d < 3; ++d) ci[d] = cell_index(x[d], a.cs[d], a.nc[d]);
   return ci[0] + a.nc[0] * (ci[1] + a.nc[1] * ci[2]);
 }
 
@@ -410,6 +422,10 @@ __global__ void k_cell_sort(CellArgs a, int ncell) {
   const int c = blockIdx.x * PBLOCK + threadIdx.x;
   if (c >= ncell) return;
   const int b = a.start[c], e = a.start[c + 1];
+  // A cell of side >= d0 holds a handful of non-overlapping spheres; a crowded
+  // cell only arises from non-finite positions and is left unsorted so that
+  // the quadratic insertion sort stays short.
+  if (e - b > 64) return;
   for (int i = b + 1; i < e; ++i) {
     const int v = a.ids[i];
     int j = i - 1;
@@ -432,10 +448,7 @@ __global__ void k_pairs(CellArgs a) {
   if (p >= a.np) return;
   const double* xp = a.ps + size_t(p) * PSTRIDE;
   int ci[3];
-  for (int d = 0; d < 3; ++d) {
-    int c = int(floor(xp[d] / a.cs[d]));
-    ci[d] = c < 0 ? 0 : (c >= a.nc[d] ? a.nc[d] - 1 : c);
-  }
+  for (int d = 0; d < 3; ++d) ci[d] = cell_index(xp[d], a.cs[d], a.nc[d]);
   double F[3] = {0, 0, 0};
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
