@@ -344,7 +344,7 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t n, u
       st32(fout + (size_t(k) * Q + j) * N, s, fs - corr);
       dev += double(real(2) * fs - corr);
     }
-    if (p < 0) continue;
+    if (p < 0 || !a.acc) continue;
     const double fl = 2.0 * wi * rho0sum + dev;  // F_link = fl c_i
     const double Fx = fl * cx, Fy = fl * cy, Fz = fl * cz;
     if (p != pid) {
@@ -658,7 +658,8 @@ static void collide_t(lb_ctx* c, const CollideArgs& a) {
     hipLaunchKernelGGL((k_collide<real, NC, false>), grid, dim3(BLOCK), 0, c->stream, a);
 }
 
-hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t* owner) {
+hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t* owner,
+                          bool forces) {
   const auto& g = c->geo;
   const auto& P = c->P;
   CollideArgs a;
@@ -667,7 +668,7 @@ hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t
   a.psi = c->B.rho;
   a.owner = owner;
   a.ps = c->nparticles ? pstate(c) : nullptr;
-  a.acc = c->nparticles ? pacc(c) : nullptr;
+  a.acc = (c->nparticles && forces) ? pacc(c) : nullptr;
   a.nx = g.nx;
   a.ny = g.ny;
   a.nz = g.nz;

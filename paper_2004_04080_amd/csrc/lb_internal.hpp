@@ -32,13 +32,13 @@ struct AdjLayout {
   size_t ckpt = 0;         // checkpoints: nckpt population buffers
   int nckpt = 0;
   size_t seg = 0;          // segment states: checkpoint_every population buffers
-  size_t lam[2] = {0, 0};  // adjoint populations (ping-pong), FP64 [ncomp][19][N]
-  size_t lam_a = 0;        // FP64 [ncomp][3][N]: adjoint of the SC acceleration
-  size_t lam_psi = 0;      // FP64 [ncomp][N]: adjoint of psi
-  size_t lam_rho = 0;      // FP64 [ncomp][N]: adjoint of local densities
-  size_t lam_j = 0;        // FP64 [3][N]: adjoint of the total momentum
+  size_t mu[2] = {0, 0};   // adjoint of the gathered populations (ping-pong), FP64 [ncomp][19][N]
+  size_t lam_a = 0;        // FP64 [ncomp][3][N]: adjoint of the Shan-Chen acceleration
+  size_t lam_psi = 0;      // FP64 [ncomp][N]: adjoint of the pseudo-potential
+  size_t winv = 0;         // FP64 [N]: 1 / (sum of w_i over fluid neighbours) of frontier solids
   size_t grad = 0;         // FP64 [3][N]: loss gradient scratch
-  size_t partials = 0;     // double[RED_BLOCKS][RED_N]
+  size_t partials = 0;     // double[blocks][4] of one reverse step
+  size_t accum = 0;        // double[4]: dL/dG, dL/dg
   size_t total = 0;
 };
 
@@ -88,7 +88,9 @@ void cell_dims(const lb_params& p, int ncell[3]);
 hipError_t launch_init_populations(lb_ctx* c, const double* rho0_dev, const double* u0_dev,
                                    uint32_t first, uint32_t count);
 hipError_t launch_density(lb_ctx* c, const void* f);
-hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t* owner);
+// forces = false leaves the sphere accumulators alone (recomputation in the reverse sweep)
+hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t* owner,
+                          bool forces = true);
 hipError_t launch_fill_walls(lb_ctx* c, const uint16_t* owner);
 hipError_t launch_get_populations(lb_ctx* c, int k, int i, uint32_t first, uint32_t count,
                                   double* out);
