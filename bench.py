@@ -58,7 +58,7 @@ def link_count(owner: np.ndarray, shape) -> tuple:
     return int(np.count_nonzero(fluid)), links
 
 
-def run_gpu(w, rho, x, precision, steps, warmup, want_roofline):
+def run_gpu(w, rho, x, precision, steps, warmup, want_roofline, want_fields=False):
     import torch
     from paper_2004_04080_amd import Lattice
     t0 = time.time()
@@ -84,10 +84,16 @@ def run_gpu(w, rho, x, precision, steps, warmup, want_roofline):
     log(f"[bench] {w.name} {precision}: {steps} steps in {ms:.1f} ms; phases {phases}")
     out = dict(ms_per_step=ms / steps, mlups=w.N * steps / (ms * 1e-3) / 1e6, phases=phases,
                flags=obs.flags, mass=obs.mass.tolist())
-    if want_roofline:
-        nfl, nlinks = link_count(lat.owner(), (w.nx, w.ny, w.nz))
-        out["fluid_nodes"] = nfl
-        out["links"] = nlinks
+    if want_roofline or want_fields:
+        own = lat.owner()
+        if want_roofline:
+            nfl, nlinks = link_count(own, (w.nx, w.ny, w.nz))
+            out["fluid_nodes"] = nfl
+            out["links"] = nlinks
+        if want_fields:
+            rho_f, u_f = lat.fields()
+            out["fields"] = (own == 0, rho_f, u_f)
+        del own
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -157,6 +163,65 @@ def cpu_baseline():
                       f"(same fluid parameters and volume fraction), {dt:.1f}s serial FP64"}
 
 
+def accuracy(a, b, steps):
+    """eps(X) = max|X_a - X_b| / max|X_b| over the fluid nodes of both runs."""
+    fa, ra, ua = a
+    fb, rb, ub = b
+    m = fa & fb
+
+    def eps(x, y):
+        return float(np.abs(x[..., m] - y[..., m]).max() / np.abs(y[..., m]).max())
+    out = {"against": "FP64 path from the same initial state (the FP64 path agrees with "
+                      "the FP64 oracle to 1e-12 on the parity cases)",
+           "steps": steps, "eps_rho": eps(ra, rb), "eps_u": eps(ua.T, ub.T)}
+    if ra.shape[0] == 2:
+        out["eps_phi"] = eps(ra[0] - ra[1], rb[0] - rb[1])
+    return {k: (float(f"{v:.3e}") if isinstance(v, float) else v) for k, v in out.items()}
+
+
+def adjoint_leg():
+    """Reverse sweep on the differentiation box (64^3, 50 fixed spheres R=4,
+    g_x = 1e-6, 500 steps, checkpoints every 50), FP64: forward and backward
+    wall time, and dL/dG against a central difference of the forward."""
+    import torch
+    import synth
+    from paper_2004_04080_amd import Lattice, Params
+    w = synth.workload("C5")
+    rho, x = w.densities(), w.centres()
+
+    def make(G, rec):
+        p = Params(w.nx, w.ny, w.nz, ncomp=2, tau=w.tau, G=G, g=w.g, precision="fp64",
+                   radius=w.radius, max_particles=len(x), particles_fixed=True,
+                   checkpoint_every=50 if rec else 0, max_record_steps=w.steps if rec else 0)
+        lat = Lattice(p, rho)
+        lat.add_particles(x)
+        return lat
+    lat = make(w.G, True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    lat.step(w.steps)
+    lat.sync()
+    t1 = time.time()
+    L, sA, sB = lat.loss(seeds=True)
+    t2 = time.time()
+    _, dG, _ = lat.backward(sA, sB)
+    t3 = time.time()
+    lat.close()
+    h = 1e-4 * w.G
+    Ls = []
+    for G in (w.G + h, w.G - h):
+        lt = make(G, False)
+        lt.step(w.steps)
+        Ls.append(lt.loss())
+        lt.close()
+    fd = (Ls[0] - Ls[1]) / (2 * h)
+    return {"workload": "C5: 64^3 two fluids + 50 fixed spheres R=4, g_x=1e-6, 500 steps, "
+                        "checkpoints every 50, FP64",
+            "forward_ms": round((t1 - t0) * 1e3, 2), "loss_ms": round((t2 - t1) * 1e3, 2),
+            "backward_ms": round((t3 - t2) * 1e3, 2), "dL_dG": dG, "dL_dG_central_difference": fd,
+            "rel_err": float(f"{abs(dG - fd) / abs(fd):.3e}")}
+
+
 def copy_probe(gib: float, reps: int = 5) -> dict:
     """A plain device-to-device copy of known size: the measured copy bandwidth,
     and the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -187,7 +252,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 run (and with it the FP32 accuracy figure)")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB and report it")
     args = ap.parse_args()
@@ -206,12 +273,21 @@ def main():
     rho = w.densities()
     x = w.centres()
     log(f"[bench] {w.name}: seeded inputs ready in {time.time() - t0:.1f}s")
-    res = run_gpu(w, rho, x, args.precision, args.steps, args.warmup, want_roofline=True)
-    fp64 = None
-    if not args.no_fp64 and args.precision == "fp32":
-        r64 = run_gpu(w, rho, x, "fp64", args.fp64_steps, 2, want_roofline=False)
-        fp64 = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "steps": args.fp64_steps,
+    check = not args.no_fp64 and args.precision == "fp32"
+    res = run_gpu(w, rho, x, args.precision, args.steps, args.warmup, want_roofline=True,
+                  want_fields=check)
+    fp64 = acc = None
+    if check:
+        # the FP64 run ends at the same step as the FP32 run, so both can be compared
+        total = args.warmup + args.steps
+        fsteps = min(args.fp64_steps, total)
+        r64 = run_gpu(w, rho, x, "fp64", fsteps, total - fsteps, want_roofline=False,
+                      want_fields=True)
+        fp64 = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "steps": fsteps,
                 "ms_per_step": round(r64["ms_per_step"], 3)}
+        acc = accuracy(res.pop("fields"), r64.pop("fields"), total)
+        log(f"[bench] FP32 against FP64 after {total} steps: {acc}")
+    adj = None if args.no_adjoint else adjoint_leg()
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     line = {
         "metric": METRIC,
@@ -233,6 +309,8 @@ def main():
         "roofline": roofline(w, res, es, args.precision),
         "cpu_baseline": cpu,
         "fp64": fp64,
+        "accuracy": acc,
+        "adjoint": adj,
         "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)
                                for k, v in res["phases"].items()},
         "flags": res["flags"],

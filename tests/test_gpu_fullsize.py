@@ -1,0 +1,142 @@
+"""One-step parity of the FP32 path at the full bench size: a 512^3 box with
+two fluids and 32,000 moving spheres of radius 5.5, built with the same
+parameters that bench.py times.
+
+The oracle cannot step the whole box, so it steps windows of it. After a few
+steps on the GPU, the state (FP32 populations read out as FP64, the map and
+the sphere records) of four 80^3 windows is handed to the oracle, which
+steps each window once as a periodic box of its own. One step reaches only a
+few nodes: streaming, the pseudo-potential stencil, the frontier fill and the
+node events each reach one node. A sphere centred up to R + 1 outside a
+window is wrapped by the oracle's periodicity onto the far side, where it
+reaches up to 2R + 1 into the window. Nodes at least 16 from every window
+face are therefore exact copies of the full-box step and are compared: the
+map bit for bit, the populations, densities, phi and u to the FP32 bounds of
+the other parity tests. Spheres whose whole surface lies in that interior
+also have their link, event and Shan-Chen forces and torques compared. Pair
+forces are switched off in the oracle windows because they act on the
+spheres only after the fluid has been updated.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import perm_gpu_for_oracle, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+W = 80          # window edge
+MARGIN = 16     # nodes next to a window face that are not compared
+TOL32 = 1e-5
+TOL32_U = 5e-5  # derivation in tests/test_gpu_parity.py
+
+
+def _window_index(origin, shape):
+    ax = [(origin[d] + np.arange(W)) % shape[d] for d in range(3)]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return (x + shape[0] * (y + shape[1] * z)).reshape(-1).astype(np.int64)
+
+
+def _eps(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_full_size_one_step_parity_on_windows():
+    import bench
+    from paper_2004_04080_amd import Lattice
+    w = synth.workload("T")
+    shape = (w.nx, w.ny, w.nz)
+    print("[fullsize] building the 512^3 state", flush=True)
+    lat = Lattice(bench.params_for(w, "fp32"), w.densities())
+    lat.add_particles(w.centres())
+    lat.step(3)
+    rng = np.random.default_rng(5)
+    origins = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(4)]
+    idx = [_window_index(o, shape) for o in origins]
+    f = lat.populations()
+    f0 = [f[:, :, i] for i in idx]
+    del f
+    own = lat.owner()
+    own0 = [own[i] for i in idx]
+    rec0 = lat.particles()
+    lat.step(1)
+    f = lat.populations()
+    f1 = [f[:, :, i] for i in idx]
+    del f
+    own = lat.owner()
+    own1 = [own[i] for i in idx]
+    rec1 = lat.particles()
+    rho_g, u_g = lat.fields()
+    rho1 = [rho_g[:, i] for i in idx]
+    u1 = [u_g[i] for i in idx]
+    del rho_g, u_g, own
+    lat.close()
+    print("[fullsize] GPU state read; stepping the oracle windows", flush=True)
+
+    perm = perm_gpu_for_oracle()
+    L = np.array(shape, dtype=float)
+    R = w.radius
+    half = (W - 1) / 2.0
+    REC = O.REC
+    inner = np.zeros((W, W, W), dtype=bool)
+    inner[MARGIN:W - MARGIN, MARGIN:W - MARGIN, MARGIN:W - MARGIN] = True
+    inner = inner.reshape(-1)
+    nspheres_checked = 0
+    for k, org in enumerate(origins):
+        # spheres that can touch the window, in window coordinates, global order kept
+        d = rec0[:, REC["x"]:REC["x"] + 3] - (np.array(org, dtype=float) + half)
+        d -= L * np.round(d / L)
+        sel = np.flatnonzero(np.all(np.abs(d) < half + R + 1.0, axis=1))
+        xw = d[sel] + half
+        local = np.zeros(len(rec0) + 1, dtype=np.int32)
+        local[sel + 1] = np.arange(1, len(sel) + 1, dtype=np.int32)
+
+        def to_local(o):
+            return np.where(o > 0, local[np.maximum(o, 0)], o)
+
+        po = O.Params(W, W, W, ncomp=2, tau=w.tau, G=w.G, sc_norm=1.0, g=w.g, radius=R,
+                      particle_density=w.particle_density, hertz_K=0.0)
+        o = O.Oracle(po, np.ones((2, W ** 3)))
+        o.add_particles(xw)
+        r = o.particles()
+        for key, n in (("v", 3), ("w", 3), ("q", 4), ("Fprev", 3), ("Tprev", 3)):
+            r[:, REC[key]:REC[key] + n] = rec0[sel, REC[key]:REC[key] + n]
+        r[:, REC["have_prev"]] = rec0[sel, REC["have_prev"]]
+        o.set_particle_state(r)
+        o.set_owner(to_local(own0[k]))
+        o.set_f(f0[k][:, perm, :])
+        o.step(1)
+
+        own_o = o.owner()
+        own_g = to_local(own1[k])
+        assert np.array_equal(own_o[inner], own_g[inner]), f"map, window {org}"
+        m = inner & (own_o == 0)
+        fo = o.f()[:, :, m]
+        fg = f1[k][:, perm, :][:, :, m]
+        ro = o.rho()[:, m]
+        rg = rho1[k][:, m]
+        e = {"f": _eps(fg, fo),
+             "rho0": _eps(rg[0], ro[0]), "rho1": _eps(rg[1], ro[1]),
+             "phi": _eps(rg[0] - rg[1], ro[0] - ro[1]),
+             "u": _eps(u1[k][m], o.u()[m])}
+        print(f"[fullsize] window {org}: {m.sum()} fluid nodes, "
+              + " ".join(f"{a} {b:.1e}" for a, b in e.items()), flush=True)
+        for key in ("f", "rho0", "rho1", "phi"):
+            assert e[key] <= TOL32, (org, key, e[key])
+        assert e["u"] <= TOL32_U, (org, e["u"])
+
+        # spheres whose links and events all fall in the compared interior
+        lo, hi = MARGIN + R + 2.0, W - 1 - MARGIN - R - 2.0
+        whole = np.flatnonzero(np.all((xw >= lo) & (xw <= hi), axis=1))
+        ro_p = o.particles()
+        for j in whole:
+            gp = rec1[sel[j]]
+            op = ro_p[j]
+            scale = op[REC["flabs"]]
+            for key in ("Fliq", "Tliq", "FSC", "TSC", "Fd", "Td", "Fc", "Tc"):
+                err = np.abs(gp[REC[key]:REC[key] + 3] - op[REC[key]:REC[key] + 3]).max() / scale
+                assert err < TOL32, (org, int(sel[j]), key, err)
+        nspheres_checked += len(whole)
+    print(f"[fullsize] spheres compared: {nspheres_checked}", flush=True)
+    assert nspheres_checked > 0
