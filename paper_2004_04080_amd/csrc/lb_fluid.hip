@@ -136,13 +136,101 @@ __device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, d
 }
 
 // ---------------------------------------------------------------------------
-// The fused step for one node: pull-gather (Eq. bgk2), moments and mixture
-// velocity (Eq. rho, vel, scvel), Shan-Chen acceleration from the
+// Bounce-back of one link and its momentum exchange. Fluid node (x, y, z),
+// with post-collision values fs_k = f*_ki and densities rho_k, has a solid
+// neighbour s = n + c_i owned by o (a sphere id + 1, or the wall). The
+// reflection of Eq. bbv / LADDFLBE with the surface velocity of Eq. UPI,
+//   f*_ki - 2 w_i rho_k (u_w . c_i) / c_s^2,
+// goes into slot (opp(i), s), the one n gathers next step; the link force of
+// Eq. LADDFORCE, sum_k [2 f*_ki - 2 w_i rho_k (u_w . c_i)/c_s^2] c_i, with the
+// constant part 2 w_i rho0_k c_i added in FP64, and its torque about the
+// sphere centre (Eq. FORCEPARTEQ, TORQUEPARTEQ) are accumulated per lane in
+// lv for sphere pid (flushed with atomics when a lane moves on to another
+// sphere). u_w = v + w x (r_w - x_p) with r_w the link midpoint.
+// ---------------------------------------------------------------------------
+template <typename real, int NC>
+__device__ __forceinline__ void link_one(const CollideArgs& a, int i, uint16_t o, uint32_t x,
+                                         uint32_t y, uint32_t z, const real fs[NC],
+                                         const real rho[NC], int& pid, double lv[7]) {
+  const uint32_t N = a.N;
+  real* __restrict__ fout = static_cast<real*>(a.fout);
+  const int cx = dir_c(PCX, i), cy = dir_c(PCY, i), cz = dir_c(PCZ, i);
+  const int j = dir_opp(i);
+  const uint32_t s = nbr_dyn(x, y, z, cx, cy, cz, a.nx, a.ny, a.nz);
+  const double wi = (cx * cx + cy * cy + cz * cz == 1) ? W1 : W2;
+  double uwx, uwy, uwz, rwx = 0, rwy = 0, rwz = 0;
+  int p = -1;
+  if (o == OWN_WALL) {
+    const bool lo = int(z) + cz == 0;
+    uwx = lo ? a.wall_lo[0] : a.wall_hi[0];
+    uwy = lo ? a.wall_lo[1] : a.wall_hi[1];
+    uwz = lo ? a.wall_lo[2] : a.wall_hi[2];
+  } else {
+    p = int(o) - 1;
+    const double* P = a.ps + size_t(p) * PSTRIDE;
+    double d;
+    d = double(x) + 0.5 * cx - P[PS_X];
+    rwx = d - a.L[0] * rint(d * a.invL[0]);
+    d = double(y) + 0.5 * cy - P[PS_X + 1];
+    rwy = d - a.L[1] * rint(d * a.invL[1]);
+    d = double(z) + 0.5 * cz - P[PS_X + 2];
+    rwz = d - a.L[2] * rint(d * a.invL[2]);
+    const double wx = P[PS_W], wy = P[PS_W + 1], wz = P[PS_W + 2];
+    uwx = P[PS_V] + (wy * rwz - wz * rwy);
+    uwy = P[PS_V + 1] + (wz * rwx - wx * rwz);
+    uwz = P[PS_V + 2] + (wx * rwy - wy * rwx);
+  }
+  const real cw = real(6.0 * wi * (uwx * cx + uwy * cy + uwz * cz));
+  double dev = 0.0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const real corr = cw * rho[k];
+    st32(fout + (size_t(k) * Q + j) * N, s, fs[k] - corr);
+    dev += double(real(2) * fs[k] - corr);
+  }
+  if (p < 0 || !a.acc) return;
+  const double rho0sum = a.rho0[0] + (NC == 2 ? a.rho0[NC - 1] : 0.0);
+  const double fl = 2.0 * wi * rho0sum + dev;  // F_link = fl c_i
+  const double Fx = fl * cx, Fy = fl * cy, Fz = fl * cz;
+  if (p != pid) {
+    if (pid >= 0) {  // this lane's links touch another sphere: flush the first one
+      double* acp = a.acc + size_t(pid) * ASTRIDE;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) unsafeAtomicAdd(acp + AC_FLIQ + c, lv[c]);
+      unsafeAtomicAdd(acp + AC_FLABS, lv[6]);
+    }
+    pid = p;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) lv[c] = 0.0;
+  }
+  lv[0] += Fx;
+  lv[1] += Fy;
+  lv[2] += Fz;
+  lv[3] += rwy * Fz - rwz * Fy;
+  lv[4] += rwz * Fx - rwx * Fz;
+  lv[5] += rwx * Fy - rwy * Fx;
+  lv[6] += fabs(fl) * (wi == W1 ? 1.0 : 1.4142135623730951);
+}
+
+// Links of one wave, gathered in LDS so that every lane takes one link at a
+// time instead of each lane walking its own (a wave would otherwise iterate
+// as often as its busiest lane has links). Entries beyond the capacity are
+// left to their lanes (see k_collide).
+constexpr int QW = 256;
+template <typename real, int NC>
+struct LinkQueue {
+  uint32_t meta[QW];  // lane | direction << 6 | owner << 11
+  real fs[NC][QW];    // f*_ki of the link's node and direction
+  uint32_t x[64], y[64], z[64];
+  real rho[NC][64];
+};
+
+// ---------------------------------------------------------------------------
+// The fused step, one thread per node: pull-gather (Eq. bgk2), moments and
+// mixture velocity (Eq. rho, vel, scvel), Shan-Chen acceleration from the
 // pseudo-potential of the neighbours (Eq. shanchen), EDM collision
-// (Eq. lbsbgk) and store; then, for every link ending on a solid node, the
-// moving-wall reflection (Eq. bbv, LADDFLBE, UPI) into the slot of that node
-// which this node gathers next step, and the link momentum exchange
-// (Eq. LADDFORCE) summed per sphere (Eq. FORCEPARTEQ, TORQUEPARTEQ).
+// (Eq. lbsbgk) and store; then the bounce-back and momentum exchange of
+// every link from a fluid node to a solid one (link_one).
 //
 // Collision in deviation form, with E_i(v) = w_i rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v):
 //   df*_i = w_i drho + E_i(u + a) + (1 - omega)(df_i - w_i drho - E_i(u)),
@@ -153,27 +241,61 @@ __device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, d
 //   S = omega drho - 1.5 rho (v.v - o u.u),
 // so each pair costs one evaluation of the two parts.
 // Every load of the node (map, gathers, pseudo-potential) is issued before
-// any branch on the map. Links are walked per lane over the set bits of the
-// node's link mask, so a wave iterates as often as its busiest lane has links.
-// A solid node writes zeros into the slots that no link fills, so together
-// with the reflections every slot of the output is written.
+// any branch on the map. A solid node writes zeros into the slots that no
+// link fills, so together with the reflections every slot of the output is
+// written. Workgroups are dealt round-robin over the 8 XCDs; the block index
+// is remapped so that each XCD sweeps one contiguous range of nodes and
+// neighbouring rows share that XCD's L2.
 // ---------------------------------------------------------------------------
 template <typename real, int NC, bool SOLIDS>
-__device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t n, uint32_t x,
-                                             uint32_t y, uint32_t z, int& pid, double lv[7]) {
+__global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
+  const uint32_t b = (blockIdx.x % 8u) * a.blocks_per_xcd + blockIdx.x / 8u;
+  const uint32_t n0 = b * BLOCK + threadIdx.x;
+  const bool valid = n0 < a.N;
   const uint32_t N = a.N;
+  const uint32_t n = valid ? n0 : N - 1;  // tail lanes mirror the last node and store nothing
+  uint32_t x, y, z;
+  node_xyz(n, a.nx, a.ny, x, y, z);
   Nbr nb(x, y, z, a.nx, a.ny, a.nz);
   const real* __restrict__ fin = static_cast<const real*>(a.fin);
   real* __restrict__ fout = static_cast<real*>(a.fout);
   const real* __restrict__ psi = static_cast<const real*>(a.psi);
+  const int lane = __lane_id();
 
+  // map: this node and the 18 neighbours; the wave's links are numbered
   uint32_t lmask = 0;
-  bool fluid = true;
+  bool fluid = valid;
+  int qbase = 0, qtotal = 0;
+  bool queued = true;
+  __shared__ LinkQueue<real, NC> lqs[SOLIDS ? BLOCK / 64 : 1];
+  LinkQueue<real, NC>& lq = lqs[SOLIDS ? threadIdx.x / 64 : 0];
   if (SOLIDS) {
-    fluid = ld32(a.owner, n) == 0;
+    fluid = valid && ld32(a.owner, n) == 0;
+    uint16_t ow[Q];
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-      if (ld32(a.owner, nb.push(i)) != 0) lmask |= 1u << i;
+    for (int i = 1; i < Q; ++i) {
+      ow[i] = ld32(a.owner, nb.push(i));
+      if (ow[i] != 0) lmask |= 1u << i;
+    }
+    const uint32_t lm = fluid ? lmask : 0u;
+    const int cnt = __popc(lm);
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
+    }
+    qbase = incl - cnt;
+    queued = qbase + cnt <= QW;
+    // entries of lanes past the capacity stay with their lanes
+    const uint64_t over = __ballot(!queued && cnt > 0);
+    qtotal = over ? __shfl(qbase, __ffsll((unsigned long long)over) - 1) : __shfl(incl, 63);
+    if (queued && lm) {
+      int pos = qbase;
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (lm & (1u << i)) lq.meta[pos++] = uint32_t(lane) | uint32_t(i) << 6 | uint32_t(ow[i]) << 11;
+    }
   }
   real f[NC][Q];
 #pragma unroll
@@ -216,14 +338,13 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t n, u
     }
   }
 
-  if (!fluid) {
-#pragma unroll
-    for (int k = 0; k < NC; ++k)
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-        if (i == 0 || (lmask & (1u << i))) st32(fout + (size_t(k) * Q + i) * N, n, real(0));
-    return;
-  }
+  // Solid lanes run the same arithmetic on whatever they gathered and store
+  // zeros through the same store instructions as the fluid lanes, into slot 0
+  // and the slots towards solid neighbours; the slots towards fluid neighbours
+  // are left to the reflections written by those neighbours. A wave that
+  // mixes fluid and solid nodes thus issues every store once.
+  const uint32_t smask = !valid ? 0u : (fluid ? 0x7FFFFu : (lmask | 1u));
+  if (!fluid) lmask = 0;  // links are walked from fluid nodes only
 
   real drho[NC], rho[NC], jx[NC], jy[NC], jz[NC];
 #pragma unroll
@@ -281,6 +402,7 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t n, u
     ocu[i] = omc * cu;
     ocu2[i] = ocu[i] * cu;
   }
+  const bool enq = SOLIDS && queued && lmask != 0;
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     const real vx = ux + ax[k], vy = uy + ay[k], vz = uz + az[k];
@@ -290,7 +412,12 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t n, u
     const real wA[2] = {real(W1) * A, real(W2) * A};
     const real wB[2] = {real(W1) * B, real(W2) * B};
     real* fk = fout + size_t(k) * Q * N;
-    st32(fk, n, omc * f[k][0] + real(1.0 / 3.0) * S);
+    auto put = [&](int i, real v) {
+      if (smask & (1u << i)) st32(fk + size_t(i) * N, n, fluid ? v : real(0));
+      // the link's post-collision value, for the lane that will take the link
+      if (enq && (lmask & (1u << i))) lq.fs[k][qbase + __popc(lmask & ((1u << i) - 1u))] = v;
+    };
+    put(0, omc * f[k][0] + real(1.0 / 3.0) * S);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       if (OPP[i] < i) continue;
@@ -298,91 +425,50 @@ __device__ __forceinline__ void collide_node(const CollideArgs& a, uint32_t n, u
       const real cv = cdot(i, vx, vy, vz);
       const real E = (cv * cv - ocu2[i]) * wA[cls] + wS[cls];
       const real D = (cv - ocu[i]) * wB[cls];
-      st32(fk + size_t(i) * N, n, omc * f[k][i] + (E + D));
-      st32(fk + size_t(OPP[i]) * N, n, omc * f[k][OPP[i]] + (E - D));
+      put(i, omc * f[k][i] + (E + D));
+      put(OPP[i], omc * f[k][OPP[i]] + (E - D));
     }
   }
   if (!SOLIDS) return;
-  const double rho0sum = a.rho0[0] + (NC == 2 ? a.rho0[NC - 1] : 0.0);
-  while (lmask) {
-    const int i = __ffs(lmask) - 1;
-    lmask &= lmask - 1u;
-    const int cx = dir_c(PCX, i), cy = dir_c(PCY, i), cz = dir_c(PCZ, i);
-    const int j = dir_opp(i);
-    const uint32_t s = nbr_dyn(x, y, z, cx, cy, cz, a.nx, a.ny, a.nz);
-    const uint16_t o = ld32(a.owner, s);
-    const double wi = (cx * cx + cy * cy + cz * cz == 1) ? W1 : W2;
-    double uwx, uwy, uwz, rwx = 0, rwy = 0, rwz = 0;
-    int p = -1;
-    if (o == OWN_WALL) {
-      const bool lo = int(z) + cz == 0;
-      uwx = lo ? a.wall_lo[0] : a.wall_hi[0];
-      uwy = lo ? a.wall_lo[1] : a.wall_hi[1];
-      uwz = lo ? a.wall_lo[2] : a.wall_hi[2];
-    } else {
-      p = int(o) - 1;
-      const double* P = a.ps + size_t(p) * PSTRIDE;
-      double d;
-      d = double(x) + 0.5 * cx - P[PS_X];
-      rwx = d - a.L[0] * rint(d * a.invL[0]);
-      d = double(y) + 0.5 * cy - P[PS_X + 1];
-      rwy = d - a.L[1] * rint(d * a.invL[1]);
-      d = double(z) + 0.5 * cz - P[PS_X + 2];
-      rwz = d - a.L[2] * rint(d * a.invL[2]);
-      const double wx = P[PS_W], wy = P[PS_W + 1], wz = P[PS_W + 2];
-      uwx = P[PS_V] + (wy * rwz - wz * rwy);
-      uwy = P[PS_V + 1] + (wz * rwx - wx * rwz);
-      uwz = P[PS_V + 2] + (wx * rwy - wy * rwx);
-    }
-    const real cw = real(6.0 * wi * (uwx * cx + uwy * cy + uwz * cz));
-    double dev = 0.0;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      // the post-collision value this thread has just stored
-      const real fs = ld32(fout + (size_t(k) * Q + i) * N, n);
-      const real corr = cw * rho[k];
-      st32(fout + (size_t(k) * Q + j) * N, s, fs - corr);
-      dev += double(real(2) * fs - corr);
-    }
-    if (p < 0 || !a.acc) continue;
-    const double fl = 2.0 * wi * rho0sum + dev;  // F_link = fl c_i
-    const double Fx = fl * cx, Fy = fl * cy, Fz = fl * cz;
-    if (p != pid) {
-      if (pid >= 0) {  // this thread's links touch another sphere: flush the first one
-        double* acp = a.acc + size_t(pid) * ASTRIDE;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) unsafeAtomicAdd(acp + AC_FLIQ + c, lv[c]);
-        unsafeAtomicAdd(acp + AC_FLABS, lv[6]);
-      }
-      pid = p;
-#pragma unroll
-      for (int c = 0; c < 7; ++c) lv[c] = 0.0;
-    }
-    lv[0] += Fx;
-    lv[1] += Fy;
-    lv[2] += Fz;
-    lv[3] += rwy * Fz - rwz * Fy;
-    lv[4] += rwz * Fx - rwx * Fz;
-    lv[5] += rwx * Fy - rwy * Fx;
-    lv[6] += fabs(fl) * (wi == W1 ? 1.0 : 1.4142135623730951);
-  }
-}
 
-// One thread per node, in node order. Workgroups are dealt round-robin over
-// the 8 XCDs; the block index is remapped so that each XCD sweeps one
-// contiguous range of nodes and neighbouring rows share that XCD's L2.
-template <typename real, int NC, bool SOLIDS>
-__global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
-  const uint32_t b = (blockIdx.x % 8u) * a.blocks_per_xcd + blockIdx.x / 8u;
-  const uint32_t n = b * BLOCK + threadIdx.x;
   int pid = -1;
   double lv[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (n < a.N) {
-    uint32_t x, y, z;
-    node_xyz(n, a.nx, a.ny, x, y, z);
-    collide_node<real, NC, SOLIDS>(a, n, x, y, z, pid, lv);
+  lq.x[lane] = x;
+  lq.y[lane] = y;
+  lq.z[lane] = z;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) lq.rho[k][lane] = rho[k];
+  // the wave's own LDS writes, in order, before any lane reads them
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int e = lane; e < qtotal; e += 64) {
+    const uint32_t m = lq.meta[e];
+    const int src = int(m & 63u), i = int((m >> 6) & 31u);
+    const uint16_t o = uint16_t(m >> 11);
+    real fs[NC], rk[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      fs[k] = lq.fs[k][e];
+      rk[k] = lq.rho[k][src];
+    }
+    link_one<real, NC>(a, i, o, lq.x[src], lq.y[src], lq.z[src], fs, rk, pid, lv);
   }
-  if (SOLIDS && a.acc) flush_links(a.acc, pid, lv);
+  if (!queued) {
+    // past the wave's capacity: this lane walks its own links, reading back
+    // the values it has just stored
+    while (lmask) {
+      const int i = __ffs(lmask) - 1;
+      lmask &= lmask - 1u;
+      real fs[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) fs[k] = ld32(fout + (size_t(k) * Q + i) * N, n);
+      const uint32_t sn = nbr_dyn(x, y, z, dir_c(PCX, i), dir_c(PCY, i), dir_c(PCZ, i), a.nx,
+                                  a.ny, a.nz);
+      link_one<real, NC>(a, i, ld32(a.owner, sn), x, y, z, fs, rho, pid, lv);
+    }
+  }
+  if (a.acc) flush_links(a.acc, pid, lv);
 }
 
 // ---------------------------------------------------------------------------

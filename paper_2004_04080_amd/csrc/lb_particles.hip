@@ -268,78 +268,108 @@ __global__ void __launch_bounds__(PBLOCK) k_events(PArgs a) {
   }
 }
 
-// Virtual densities on the frontier of sphere p (Eq. soliddens) and the
-// Shan-Chen force those nodes feel (Eq. shanchen2), summed into F_SC, T_SC.
-template <typename real>
-__global__ void __launch_bounds__(PBLOCK) k_fill_sphere(PArgs a) {
-  const int p = blockIdx.x;
-  const double* P = a.ps + size_t(p) * PSTRIDE;
-  const double xc[3] = {P[PS_X], P[PS_X + 1], P[PS_X + 2]};
-  const Box b = sphere_box(xc, a.R);
-  const uint16_t me = uint16_t(p + 1);
-  real* psi = static_cast<real*>(a.psi);
-  const uint32_t N = a.N;
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
-    uint32_t n = 0, mask = 0;
-    {
-      int x, y, z;
-      box_node(b, t, x, y, z);
-      const uint32_t wx = wrap_int(x, a.nx), wy = wrap_int(y, a.ny), wz = wrap_int(z, a.nz);
-      n = wx + a.nx * (wy + a.ny * wz);
-      if (a.own_new[n] == me) {
-        Nbr nb(wx, wy, wz, a.nx, a.ny, a.nz);
+// Wave-level segmented sum of per-lane contributions keyed by sphere id, then
+// one FP64 atomic per (wave, sphere, component) into acc[p][off + 0..NV-1].
+// Every lane of the wave calls it (lanes without a contribution pass pid < 0).
+template <int NV>
+__device__ __forceinline__ void flush_sphere_sums(double* __restrict__ acc, int off, int pid,
+                                                  const double v[NV]) {
+  const int lane = __lane_id();
+  uint64_t pending = __ballot(pid >= 0);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int lp = __shfl(pid, leader);
+    const bool mine = pid == lp;
+    double s[NV];
 #pragma unroll
-        for (int i = 1; i < Q; ++i)
-          if (a.own_new[nb.push(i)] == 0) mask |= 1u << i;
-        double wsum = 0.0, s[2] = {0, 0}, Ws[3] = {0, 0, 0}, g[2][3] = {{0, 0, 0}, {0, 0, 0}};
-        for (int i = 1; i < Q; ++i) {
-          if (!(mask & (1u << i))) continue;
-          const uint32_t m = nb.push(i);
-          wsum += WQ[i];
-          Ws[0] += WQ[i] * CX[i];
-          Ws[1] += WQ[i] * CY[i];
-          Ws[2] += WQ[i] * CZ[i];
-          for (int k = 0; k < a.ncomp; ++k) {
-            const double dp = double(psi[size_t(k) * N + m]);
-            s[k] += WQ[i] * dp;
-            g[k][0] += WQ[i] * dp * CX[i];
-            g[k][1] += WQ[i] * dp * CY[i];
-            g[k][2] += WQ[i] * dp * CZ[i];
-          }
+    for (int c = 0; c < NV; ++c) s[c] = mine ? v[c] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) s[c] += __shfl_xor(s[c], o);
+    if (lane == leader) {
+      double* A = acc + size_t(lp) * ASTRIDE + off;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) unsafeAtomicAdd(A + c, s[c]);
+    }
+    if (mine) pid = -1;
+    pending = __ballot(pid >= 0);
+  }
+}
+
+// Virtual densities on the sphere frontier (Eq. soliddens) and the Shan-Chen
+// force those nodes feel (Eq. shanchen2), one thread per node: a solid node
+// of a sphere with at least one fluid neighbour takes the w-weighted mean of
+// the pseudo-potential of those neighbours; with forces on, its force
+// F = -G s sum_k psi_k(n) sum_{i: n+c_i fluid} w_i psi_kbar(n+c_i) c_i and the
+// torque about the sphere centre are summed into F_SC, T_SC of its sphere.
+// Wall nodes are left to the wall fill.
+template <typename real, int NC>
+__global__ void __launch_bounds__(PBLOCK) k_fill_nodes(PArgs a) {
+  const uint32_t n = blockIdx.x * PBLOCK + threadIdx.x;
+  int pid = -1;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  const uint16_t o = n < a.N ? a.own_new[n] : uint16_t(0);
+  if (o != 0 && o != OWN_WALL) {
+    uint32_t x, y, z;
+    node_xyz(n, uint32_t(a.nx), uint32_t(a.ny), x, y, z);
+    Nbr nb(x, y, z, uint32_t(a.nx), uint32_t(a.ny), uint32_t(a.nz));
+    uint32_t mask = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      if (a.own_new[nb.push(i)] == 0) mask |= 1u << i;
+    if (mask) {
+      real* psi = static_cast<real*>(a.psi);
+      const uint32_t N = a.N;
+      double wsum = 0.0, s[NC], Ws[3] = {0, 0, 0}, g[NC][3];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) s[k] = g[k][0] = g[k][1] = g[k][2] = 0.0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        if (!(mask & (1u << i))) continue;
+        const uint32_t m = nb.push(i);
+        wsum += WQ[i];
+        Ws[0] += WQ[i] * CX[i];
+        Ws[1] += WQ[i] * CY[i];
+        Ws[2] += WQ[i] * CZ[i];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          const double dp = double(psi[size_t(k) * N + m]);
+          s[k] += WQ[i] * dp;
+          g[k][0] += WQ[i] * dp * CX[i];
+          g[k][1] += WQ[i] * dp * CY[i];
+          g[k][2] += WQ[i] * dp * CZ[i];
         }
-        if (mask) {
-          double dv[2];
-          for (int k = 0; k < a.ncomp; ++k) {
-            dv[k] = a.zeta[k] * a.rho0[k] + (1.0 + a.zeta[k]) * s[k] / wsum;
-            psi[size_t(k) * N + n] = real(dv[k]);
-          }
-          if (a.ncomp == 2) {
-            double F[3] = {0, 0, 0};
-            for (int k = 0; k < 2; ++k) {
-              const int kb = 1 - k;
-              const double pk = a.rho0[k] + dv[k];
-              for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + g[kb][c]);
-            }
-            const double d[3] = {min_image(double(wx) - xc[0], a.L[0]),
-                                 min_image(double(wy) - xc[1], a.L[1]),
-                                 min_image(double(wz) - xc[2], a.L[2])};
-            v[0] += F[0];
-            v[1] += F[1];
-            v[2] += F[2];
-            v[3] += d[1] * F[2] - d[2] * F[1];
-            v[4] += d[2] * F[0] - d[0] * F[2];
-            v[5] += d[0] * F[1] - d[1] * F[0];
-          }
+      }
+      double dv[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        dv[k] = a.zeta[k] * a.rho0[k] + (1.0 + a.zeta[k]) * s[k] / wsum;
+        psi[size_t(k) * N + n] = real(dv[k]);
+      }
+      if (NC == 2 && a.acc) {
+        double F[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          const int kb = NC - 1 - k;
+          const double pk = a.rho0[k] + dv[k];
+          for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + g[kb][c]);
         }
+        pid = int(o) - 1;
+        const double* P = a.ps + size_t(pid) * PSTRIDE;
+        const double d[3] = {min_image(double(x) - P[PS_X], a.L[0]),
+                             min_image(double(y) - P[PS_X + 1], a.L[1]),
+                             min_image(double(z) - P[PS_X + 2], a.L[2])};
+        v[0] = F[0];
+        v[1] = F[1];
+        v[2] = F[2];
+        v[3] = d[1] * F[2] - d[2] * F[1];
+        v[4] = d[2] * F[0] - d[0] * F[2];
+        v[5] = d[0] * F[1] - d[1] * F[0];
       }
     }
   }
-  block_sum<6>(v);
-  if (threadIdx.x == 0 && a.acc) {
-    double* A = a.acc + size_t(p) * ASTRIDE;
-    for (int c = 0; c < 6; ++c) A[AC_FSC + c] = v[c];
-  }
+  if (NC == 2 && a.acc) flush_sphere_sums<6>(a.acc, AC_FSC, pid, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -651,10 +681,15 @@ hipError_t launch_step_particles_pre(lb_ctx* c) {
 hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces) {
   PArgs a = pargs(c, const_cast<uint16_t*>(owner), owner);
   if (!forces) a.acc = nullptr;  // psi only: leave the force terms alone
-  if (c->geo.prec == LB_FP64)
-    hipLaunchKernelGGL(k_fill_sphere<double>, dim3(c->nparticles), dim3(PBLOCK), 0, c->stream, a);
-  else
-    hipLaunchKernelGGL(k_fill_sphere<float>, dim3(c->nparticles), dim3(PBLOCK), 0, c->stream, a);
+  const dim3 grid((c->geo.N + PBLOCK - 1) / PBLOCK);
+  const bool two = c->geo.ncomp == 2;
+  if (c->geo.prec == LB_FP64) {
+    if (two) hipLaunchKernelGGL((k_fill_nodes<double, 2>), grid, dim3(PBLOCK), 0, c->stream, a);
+    else hipLaunchKernelGGL((k_fill_nodes<double, 1>), grid, dim3(PBLOCK), 0, c->stream, a);
+  } else {
+    if (two) hipLaunchKernelGGL((k_fill_nodes<float, 2>), grid, dim3(PBLOCK), 0, c->stream, a);
+    else hipLaunchKernelGGL((k_fill_nodes<float, 1>), grid, dim3(PBLOCK), 0, c->stream, a);
+  }
   return hipGetLastError();
 }
 
