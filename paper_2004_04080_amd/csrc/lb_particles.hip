@@ -58,7 +58,7 @@ struct PArgs {
   void* psi;
   int nx, ny, nz;
   uint32_t N;
-  double L[3];
+  double L[3], invL[3];
   double R;
   double rho0[2];
   double zeta[2];
@@ -268,6 +268,23 @@ __global__ void __launch_bounds__(PBLOCK) k_events(PArgs a) {
   }
 }
 
+// Direction sets as bit masks over the 18 moving directions: axis and
+// diagonal directions, and per axis those with c = +1 / -1 in each class.
+constexpr uint32_t dir_set(int axis, int sign, int cls) {
+  uint32_t m = 0;
+  for (int i = 1; i < Q; ++i) {
+    const int c = axis == 0 ? CX[i] : (axis == 1 ? CY[i] : CZ[i]);
+    const bool ax = axis_dir(i);
+    if ((sign == 0 || c == sign) && ((cls == 1) == ax)) m |= 1u << i;
+  }
+  return m;
+}
+constexpr uint32_t kAxisDirs = dir_set(0, 0, 1), kDiagDirs = dir_set(0, 0, 2);
+constexpr uint32_t kPos1[3] = {dir_set(0, 1, 1), dir_set(1, 1, 1), dir_set(2, 1, 1)};
+constexpr uint32_t kNeg1[3] = {dir_set(0, -1, 1), dir_set(1, -1, 1), dir_set(2, -1, 1)};
+constexpr uint32_t kPos2[3] = {dir_set(0, 1, 2), dir_set(1, 1, 2), dir_set(2, 1, 2)};
+constexpr uint32_t kNeg2[3] = {dir_set(0, -1, 2), dir_set(1, -1, 2), dir_set(2, -1, 2)};
+
 // Wave-level segmented sum of per-lane contributions keyed by sphere id, then
 // one FP64 atomic per (wave, sphere, component) into acc[p][off + 0..NV-1].
 // Every lane of the wave calls it (lanes without a contribution pass pid < 0).
@@ -321,30 +338,42 @@ __global__ void __launch_bounds__(PBLOCK) k_fill_nodes(PArgs a) {
     if (mask) {
       real* psi = static_cast<real*>(a.psi);
       const uint32_t N = a.N;
-      double wsum = 0.0, s[NC], Ws[3] = {0, 0, 0}, g[NC][3];
+      // weights over the fluid neighbours from the mask alone: sum w_i and
+      // sum w_i c_i, axis (1/18) and diagonal (1/36) directions counted apart
+      // (__popc is unsigned: counts are taken as int before differencing)
+      auto cnt = [&](uint32_t set) { return int(__popc(mask & set)); };
+      const double wsum = W1 * cnt(kAxisDirs) + W2 * cnt(kDiagDirs);
+      double Ws[3];
 #pragma unroll
-      for (int k = 0; k < NC; ++k) s[k] = g[k][0] = g[k][1] = g[k][2] = 0.0;
+      for (int d = 0; d < 3; ++d)
+        Ws[d] = W1 * (cnt(kPos1[d]) - cnt(kNeg1[d])) + W2 * (cnt(kPos2[d]) - cnt(kNeg2[d]));
+      // sum_i w_i psi_k(n + c_i) and sum_i w_i psi_k(n + c_i) c_i over the
+      // fluid neighbours, in the storage precision, by weight class
+      double sk[NC], gk[NC][3];
 #pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        if (!(mask & (1u << i))) continue;
-        const uint32_t m = nb.push(i);
-        wsum += WQ[i];
-        Ws[0] += WQ[i] * CX[i];
-        Ws[1] += WQ[i] * CY[i];
-        Ws[2] += WQ[i] * CZ[i];
+      for (int k = 0; k < NC; ++k) {
+        const real* pk = psi + size_t(k) * N;
+        real s1 = 0, s2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-          const double dp = double(psi[size_t(k) * N + m]);
-          s[k] += WQ[i] * dp;
-          g[k][0] += WQ[i] * dp * CX[i];
-          g[k][1] += WQ[i] * dp * CY[i];
-          g[k][2] += WQ[i] * dp * CZ[i];
+        for (int i = 1; i < Q; ++i) {
+          const real pv = (mask & (1u << i)) ? pk[nb.push(i)] : real(0);
+          const int c[3] = {CX[i], CY[i], CZ[i]};
+          if (axis_dir(i)) s1 += pv;
+          else s2 += pv;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            if (!c[d]) continue;
+            if (axis_dir(i)) g1[d] += c[d] > 0 ? pv : -pv;
+            else g2[d] += c[d] > 0 ? pv : -pv;
+          }
         }
+        sk[k] = W1 * double(s1) + W2 * double(s2);
+        for (int d = 0; d < 3; ++d) gk[k][d] = W1 * double(g1[d]) + W2 * double(g2[d]);
       }
       double dv[NC];
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
-        dv[k] = a.zeta[k] * a.rho0[k] + (1.0 + a.zeta[k]) * s[k] / wsum;
+        dv[k] = a.zeta[k] * a.rho0[k] + (1.0 + a.zeta[k]) * sk[k] / wsum;
         psi[size_t(k) * N + n] = real(dv[k]);
       }
       if (NC == 2 && a.acc) {
@@ -353,13 +382,12 @@ __global__ void __launch_bounds__(PBLOCK) k_fill_nodes(PArgs a) {
         for (int k = 0; k < NC; ++k) {
           const int kb = NC - 1 - k;
           const double pk = a.rho0[k] + dv[k];
-          for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + g[kb][c]);
+          for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + gk[kb][c]);
         }
         pid = int(o) - 1;
         const double* P = a.ps + size_t(pid) * PSTRIDE;
-        const double d[3] = {min_image(double(x) - P[PS_X], a.L[0]),
-                             min_image(double(y) - P[PS_X + 1], a.L[1]),
-                             min_image(double(z) - P[PS_X + 2], a.L[2])};
+        double d[3] = {double(x) - P[PS_X], double(y) - P[PS_X + 1], double(z) - P[PS_X + 2]};
+        for (int c = 0; c < 3; ++c) d[c] -= a.L[c] * rint(d[c] * a.invL[c]);
         v[0] = F[0];
         v[1] = F[1];
         v[2] = F[2];
@@ -608,6 +636,7 @@ static PArgs pargs(lb_ctx* c, uint16_t* own_new, const uint16_t* own_old) {
   a.L[0] = c->geo.nx;
   a.L[1] = c->geo.ny;
   a.L[2] = c->geo.nz;
+  for (int d = 0; d < 3; ++d) a.invL[d] = 1.0 / a.L[d];
   a.R = c->P.radius;
   a.ncomp = c->geo.ncomp;
   for (int k = 0; k < 2; ++k) {
