@@ -217,10 +217,15 @@ __device__ __forceinline__ void link_one(const CollideArgs& a, int i, uint16_t o
 // as often as its busiest lane has links). Entries beyond the capacity are
 // left to their lanes (see k_collide).
 constexpr int QW = 256;
+// With 4-byte values every lane keeps all its post-collision values, indexed
+// by (direction, lane), which costs one LDS store per value and no index
+// arithmetic; 8-byte values are packed by link to stay within the LDS budget.
+template <typename real>
+constexpr bool kDenseLinks = sizeof(real) == 4;
 template <typename real, int NC>
 struct LinkQueue {
   uint32_t meta[QW];  // lane | direction << 6 | owner << 11
-  real fs[NC][QW];    // f*_ki of the link's node and direction
+  real fs[NC][kDenseLinks<real> ? Q * 64 : QW];
   uint32_t x[64], y[64], z[64];
   real rho[NC][64];
 };
@@ -415,7 +420,11 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
     auto put = [&](int i, real v) {
       if (smask & (1u << i)) st32(fk + size_t(i) * N, n, fluid ? v : real(0));
       // the link's post-collision value, for the lane that will take the link
-      if (enq && (lmask & (1u << i))) lq.fs[k][qbase + __popc(lmask & ((1u << i) - 1u))] = v;
+      if (kDenseLinks<real>) {
+        if (SOLIDS) lq.fs[k][i * 64 + lane] = v;
+      } else if (enq && (lmask & (1u << i))) {
+        lq.fs[k][qbase + __popc(lmask & ((1u << i) - 1u))] = v;
+      }
     };
     put(0, omc * f[k][0] + real(1.0 / 3.0) * S);
 #pragma unroll
@@ -449,7 +458,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
     real fs[NC], rk[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      fs[k] = lq.fs[k][e];
+      fs[k] = lq.fs[k][kDenseLinks<real> ? i * 64 + src : e];
       rk[k] = lq.rho[k][src];
     }
     link_one<real, NC>(a, i, o, lq.x[src], lq.y[src], lq.z[src], fs, rk, pid, lv);
