@@ -116,8 +116,10 @@ __device__ __forceinline__ void node_xyz(uint32_t n, uint32_t nx, uint32_t ny, u
   z = t / ny;
 }
 
+// Minimum image of a periodic displacement. |d| < L/2 needs no division and
+// gives the same value as the general form (rint(d/L) is then zero).
 __device__ __forceinline__ double min_image(double d, double L) {
-  return d - L * rint(d / L);
+  return fabs(d + d) < L ? d : d - L * rint(d / L);
 }
 
 __device__ __forceinline__ int wrap_int(int v, int L) {

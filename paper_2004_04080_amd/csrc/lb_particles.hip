@@ -137,6 +137,11 @@ __global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which) {
   const double c[3] = {P[which], P[which + 1], P[which + 2]};
   const Box b = sphere_box(c, a.R);
   const double R2 = a.R * a.R;
+  if (which == PS_X && threadIdx.x == 0 && a.flags) {
+    // speed limit of the moving-boundary scheme: at most half a node per step
+    const double vmax = fmax(fabs(P[PS_V]), fmax(fabs(P[PS_V + 1]), fabs(P[PS_V + 2])));
+    if (!(vmax <= 0.5)) atomicOr(a.flags, 1);
+  }
   for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
     int x, y, z;
     box_node(b, t, x, y, z);
@@ -149,141 +154,6 @@ __global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which) {
       claim(a.own_new, uint32_t(wx) + a.nx * (uint32_t(wy) + a.ny * uint32_t(wz)), uint16_t(p + 1));
   }
 }
-
-// Fluid-node destruction (Eq. distr) and creation (Eq. creat) for sphere p.
-// Destroyed nodes hand their bare momentum sum_k j_k to the sphere; created
-// nodes get f_eq(rho_bar_k, u_w) in the slots they gather from, with rho_bar
-// the w-weighted mean over neighbours fluid in both maps.
-template <typename real>
-__global__ void __launch_bounds__(PBLOCK) k_events(PArgs a) {
-  const int p = blockIdx.x;
-  const double* P = a.ps + size_t(p) * PSTRIDE;
-  const double xc[3] = {P[PS_X], P[PS_X + 1], P[PS_X + 2]};
-  // the old centre, unwrapped next to the new one
-  double xo[3], lo[3], hi[3];
-  for (int d = 0; d < 3; ++d) {
-    xo[d] = xc[d] + min_image(P[PS_XRA + d] - xc[d], a.L[d]);
-    lo[d] = fmin(xc[d], xo[d]);
-    hi[d] = fmax(xc[d], xo[d]);
-  }
-  // A sphere within the speed limit moves at most 1/2 per axis and step; a
-  // larger (or non-finite) displacement raises the speed flag and skips the
-  // events, which keeps the box (and the kernel's run time) bounded.
-  bool jump = false;
-  for (int d = 0; d < 3; ++d) jump = jump || !(hi[d] - lo[d] <= 1.0);
-  if (jump && threadIdx.x == 0) atomicOr(a.flags, 1);
-  Box b;
-  b.total = 1;
-  for (int d = 0; d < 3; ++d) {
-    if (jump || !isfinite(lo[d]) || !isfinite(hi[d]) || fabs(lo[d]) > 1e7 || fabs(hi[d]) > 1e7) {
-      b.total = 0;
-      b.lo[d] = 0;
-      b.n[d] = 0;
-      continue;
-    }
-    b.lo[d] = int(floor(lo[d] - a.R));
-    b.n[d] = int(ceil(hi[d] + a.R)) - b.lo[d] + 1;
-    b.total *= b.n[d];
-  }
-  if (threadIdx.x == 0) {
-    const double vmax = fmax(fabs(P[PS_V]), fmax(fabs(P[PS_V + 1]), fabs(P[PS_V + 2])));
-    if (!(vmax <= 0.5)) atomicOr(a.flags, 1);
-  }
-  const uint16_t me = uint16_t(p + 1);
-  real* fin = static_cast<real*>(a.fin);
-  real* psi = static_cast<real*>(a.psi);
-  const uint32_t N = a.N;
-  double v[12];
-  for (int c = 0; c < 12; ++c) v[c] = 0.0;
-  for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
-    int x, y, z;
-    box_node(b, t, x, y, z);
-    const uint32_t wx = wrap_int(x, a.nx), wy = wrap_int(y, a.ny), wz = wrap_int(z, a.nz);
-    const uint32_t n = wx + a.nx * (wy + a.ny * wz);
-    const uint16_t o = a.own_old[n], w = a.own_new[n];
-    const bool destroyed = (o == 0 && w == me);
-    const bool created = (o == me && w == 0);
-    if (!destroyed && !created) continue;
-    Nbr nb(wx, wy, wz, a.nx, a.ny, a.nz);
-    const double d[3] = {min_image(double(wx) - xc[0], a.L[0]),
-                         min_image(double(wy) - xc[1], a.L[1]),
-                         min_image(double(wz) - xc[2], a.L[2])};
-    if (destroyed) {
-      double J[3] = {0, 0, 0};
-      for (int k = 0; k < a.ncomp; ++k)
-        for (int i = 0; i < Q; ++i) {
-          const double fv = double(fin[(size_t(k) * Q + i) * N + nb.pull(i)]);
-          J[0] += fv * CX[i];
-          J[1] += fv * CY[i];
-          J[2] += fv * CZ[i];
-        }
-      v[0] += J[0];
-      v[1] += J[1];
-      v[2] += J[2];
-      v[3] += d[1] * J[2] - d[2] * J[1];
-      v[4] += d[2] * J[0] - d[0] * J[2];
-      v[5] += d[0] * J[1] - d[1] * J[0];
-    } else {
-      const double wx_ = P[PS_W], wy_ = P[PS_W + 1], wz_ = P[PS_W + 2];
-      const double uw[3] = {P[PS_V] + (wy_ * d[2] - wz_ * d[1]),
-                            P[PS_V + 1] + (wz_ * d[0] - wx_ * d[2]),
-                            P[PS_V + 2] + (wx_ * d[1] - wy_ * d[0])};
-      double wsum = 0.0, s[2] = {0.0, 0.0};
-      for (int i = 1; i < Q; ++i) {
-        const uint32_t m = nb.push(i);
-        if (a.own_old[m] != 0 || a.own_new[m] != 0) continue;
-        wsum += WQ[i];
-        for (int k = 0; k < a.ncomp; ++k) s[k] += WQ[i] * double(psi[size_t(k) * N + m]);
-      }
-      const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
-      double tot = 0.0;
-      for (int k = 0; k < a.ncomp; ++k) {
-        // deviation of the created density from rho0_k
-        const double dr = wsum > 0.0 ? s[k] / wsum : a.rho_fb[k] - a.rho0[k];
-        const double rb = a.rho0[k] + dr;
-        tot += rb;
-        for (int i = 0; i < Q; ++i) {
-          const double cu = CX[i] * uw[0] + CY[i] * uw[1] + CZ[i] * uw[2];
-          fin[(size_t(k) * Q + i) * N + nb.pull(i)] =
-              real(WQ[i] * dr + WQ[i] * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-        }
-        psi[size_t(k) * N + n] = real(dr);
-      }
-      const double M[3] = {tot * uw[0], tot * uw[1], tot * uw[2]};
-      v[6] -= M[0];
-      v[7] -= M[1];
-      v[8] -= M[2];
-      v[9] -= d[1] * M[2] - d[2] * M[1];
-      v[10] -= d[2] * M[0] - d[0] * M[2];
-      v[11] -= d[0] * M[1] - d[1] * M[0];
-    }
-  }
-  block_sum<12>(v);
-  if (threadIdx.x == 0) {
-    double* A = a.acc + size_t(p) * ASTRIDE;
-    for (int c = 0; c < 6; ++c) {
-      A[AC_FD + c] = v[c];
-      A[AC_FC + c] = v[6 + c];
-    }
-  }
-}
-
-// Direction sets as bit masks over the 18 moving directions: axis and
-// diagonal directions, and per axis those with c = +1 / -1 in each class.
-constexpr uint32_t dir_set(int axis, int sign, int cls) {
-  uint32_t m = 0;
-  for (int i = 1; i < Q; ++i) {
-    const int c = axis == 0 ? CX[i] : (axis == 1 ? CY[i] : CZ[i]);
-    const bool ax = axis_dir(i);
-    if ((sign == 0 || c == sign) && ((cls == 1) == ax)) m |= 1u << i;
-  }
-  return m;
-}
-constexpr uint32_t kAxisDirs = dir_set(0, 0, 1), kDiagDirs = dir_set(0, 0, 2);
-constexpr uint32_t kPos1[3] = {dir_set(0, 1, 1), dir_set(1, 1, 1), dir_set(2, 1, 1)};
-constexpr uint32_t kNeg1[3] = {dir_set(0, -1, 1), dir_set(1, -1, 1), dir_set(2, -1, 1)};
-constexpr uint32_t kPos2[3] = {dir_set(0, 1, 2), dir_set(1, 1, 2), dir_set(2, 1, 2)};
-constexpr uint32_t kNeg2[3] = {dir_set(0, -1, 2), dir_set(1, -1, 2), dir_set(2, -1, 2)};
 
 // Wave-level segmented sum of per-lane contributions keyed by sphere id, then
 // one FP64 atomic per (wave, sphere, component) into acc[p][off + 0..NV-1].
@@ -313,6 +183,111 @@ __device__ __forceinline__ void flush_sphere_sums(double* __restrict__ acc, int 
     pending = __ballot(pid >= 0);
   }
 }
+
+// Fluid-node destruction (Eq. distr) and creation (Eq. creat), one thread per
+// node, from the map of the current populations (own_old) and the new map
+// (own_new). A destroyed node hands its bare momentum sum_k j_k to its new
+// sphere; a created node gets f_eq(rho_bar_k, u_w) in the slots it gathers
+// from, with rho_bar the w-weighted mean over the neighbours fluid in both
+// maps, and the sphere it left loses the momentum sum_k rho_bar_k u_w. Both
+// are summed per sphere into F_d, T_d, F_c, T_c (wave-segmented sums, then
+// FP64 atomics; the accumulators are cleared at the start of the step).
+template <typename real, int NC>
+__global__ void __launch_bounds__(PBLOCK) k_events(PArgs a) {
+  const uint32_t n = blockIdx.x * PBLOCK + threadIdx.x;
+  int pid = -1;
+  double v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = 0.0;
+  const uint16_t o = n < a.N ? a.own_old[n] : uint16_t(0);
+  const uint16_t w = n < a.N ? a.own_new[n] : uint16_t(0);
+  const bool destroyed = o == 0 && w != 0 && w != OWN_WALL;
+  const bool created = w == 0 && o != 0 && o != OWN_WALL;
+  if (destroyed || created) {
+    pid = int(destroyed ? w : o) - 1;
+    const double* P = a.ps + size_t(pid) * PSTRIDE;
+    uint32_t x, y, z;
+    node_xyz(n, uint32_t(a.nx), uint32_t(a.ny), x, y, z);
+    Nbr nb(x, y, z, uint32_t(a.nx), uint32_t(a.ny), uint32_t(a.nz));
+    const double d[3] = {min_image(double(x) - P[PS_X], a.L[0]),
+                         min_image(double(y) - P[PS_X + 1], a.L[1]),
+                         min_image(double(z) - P[PS_X + 2], a.L[2])};
+    real* fin = static_cast<real*>(a.fin);
+    real* psi = static_cast<real*>(a.psi);
+    const uint32_t N = a.N;
+    if (destroyed) {
+      double J[3] = {0, 0, 0};
+      for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const double fv = double(fin[(size_t(k) * Q + i) * N + nb.pull(i)]);
+          J[0] += fv * CX[i];
+          J[1] += fv * CY[i];
+          J[2] += fv * CZ[i];
+        }
+      v[0] = J[0];
+      v[1] = J[1];
+      v[2] = J[2];
+      v[3] = d[1] * J[2] - d[2] * J[1];
+      v[4] = d[2] * J[0] - d[0] * J[2];
+      v[5] = d[0] * J[1] - d[1] * J[0];
+    } else {
+      const double wx_ = P[PS_W], wy_ = P[PS_W + 1], wz_ = P[PS_W + 2];
+      const double uw[3] = {P[PS_V] + (wy_ * d[2] - wz_ * d[1]),
+                            P[PS_V + 1] + (wz_ * d[0] - wx_ * d[2]),
+                            P[PS_V + 2] + (wx_ * d[1] - wy_ * d[0])};
+      double wsum = 0.0, s[NC];
+      for (int k = 0; k < NC; ++k) s[k] = 0.0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const uint32_t m = nb.push(i);
+        if (a.own_old[m] != 0 || a.own_new[m] != 0) continue;
+        wsum += WQ[i];
+        for (int k = 0; k < NC; ++k) s[k] += WQ[i] * double(psi[size_t(k) * N + m]);
+      }
+      const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+      double tot = 0.0;
+      for (int k = 0; k < NC; ++k) {
+        // deviation of the created density from rho0_k
+        const double dr = wsum > 0.0 ? s[k] / wsum : a.rho_fb[k] - a.rho0[k];
+        const double rb = a.rho0[k] + dr;
+        tot += rb;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const double cu = CX[i] * uw[0] + CY[i] * uw[1] + CZ[i] * uw[2];
+          fin[(size_t(k) * Q + i) * N + nb.pull(i)] =
+              real(WQ[i] * dr + WQ[i] * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        }
+        psi[size_t(k) * N + n] = real(dr);
+      }
+      const double M[3] = {tot * uw[0], tot * uw[1], tot * uw[2]};
+      v[6] = -M[0];
+      v[7] = -M[1];
+      v[8] = -M[2];
+      v[9] = -(d[1] * M[2] - d[2] * M[1]);
+      v[10] = -(d[2] * M[0] - d[0] * M[2]);
+      v[11] = -(d[0] * M[1] - d[1] * M[0]);
+    }
+  }
+  flush_sphere_sums<12>(a.acc, AC_FD, pid, v);
+}
+
+// Direction sets as bit masks over the 18 moving directions: axis and
+// diagonal directions, and per axis those with c = +1 / -1 in each class.
+constexpr uint32_t dir_set(int axis, int sign, int cls) {
+  uint32_t m = 0;
+  for (int i = 1; i < Q; ++i) {
+    const int c = axis == 0 ? CX[i] : (axis == 1 ? CY[i] : CZ[i]);
+    const bool ax = axis_dir(i);
+    if ((sign == 0 || c == sign) && ((cls == 1) == ax)) m |= 1u << i;
+  }
+  return m;
+}
+constexpr uint32_t kAxisDirs = dir_set(0, 0, 1), kDiagDirs = dir_set(0, 0, 2);
+constexpr uint32_t kPos1[3] = {dir_set(0, 1, 1), dir_set(1, 1, 1), dir_set(2, 1, 1)};
+constexpr uint32_t kNeg1[3] = {dir_set(0, -1, 1), dir_set(1, -1, 1), dir_set(2, -1, 1)};
+constexpr uint32_t kPos2[3] = {dir_set(0, 1, 2), dir_set(1, 1, 2), dir_set(2, 1, 2)};
+constexpr uint32_t kNeg2[3] = {dir_set(0, -1, 2), dir_set(1, -1, 2), dir_set(2, -1, 2)};
 
 // Virtual densities on the sphere frontier (Eq. soliddens) and the Shan-Chen
 // force those nodes feel (Eq. shanchen2), one thread per node: a solid node
@@ -671,10 +646,15 @@ hipError_t launch_step_particles_pre(lb_ctx* c) {
   const dim3 gp(c->nparticles), bp(PBLOCK);
   hipLaunchKernelGGL(k_unraster, gp, bp, 0, c->stream, a, int(PS_XRB));
   hipLaunchKernelGGL(k_raster, gp, bp, 0, c->stream, a, int(PS_X));
-  if (c->geo.prec == LB_FP64)
-    hipLaunchKernelGGL(k_events<double>, gp, bp, 0, c->stream, a);
-  else
-    hipLaunchKernelGGL(k_events<float>, gp, bp, 0, c->stream, a);
+  const dim3 gn((c->geo.N + PBLOCK - 1) / PBLOCK);
+  const bool two = c->geo.ncomp == 2;
+  if (c->geo.prec == LB_FP64) {
+    if (two) hipLaunchKernelGGL((k_events<double, 2>), gn, bp, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_events<double, 1>), gn, bp, 0, c->stream, a);
+  } else {
+    if (two) hipLaunchKernelGGL((k_events<float, 2>), gn, bp, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_events<float, 1>), gn, bp, 0, c->stream, a);
+  }
   // Hertz pairs through the cell list
   CellArgs ca;
   ca.ps = pstate(c);
