@@ -255,6 +255,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 run (and with it the FP32 accuracy figure)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--workloads", default="",
+                    help="comma-separated further boxes (C2,C3,C4,MT0) timed after the main "
+                         "one and reported under other_workloads (FP32, same step counts)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB and report it")
     args = ap.parse_args()
@@ -288,6 +291,20 @@ def main():
         acc = accuracy(res.pop("fields"), r64.pop("fields"), total)
         log(f"[bench] FP32 against FP64 after {total} steps: {acc}")
     adj = None if args.no_adjoint else adjoint_leg()
+    others = []
+    for name in [v for v in args.workloads.split(",") if v]:
+        wo = synth.workload(name)
+        ro = run_gpu(wo, wo.densities(), wo.centres(), args.precision, args.steps, args.warmup,
+                     want_roofline=True)
+        rl = roofline(wo, ro, es, args.precision)
+        others.append({"workload": f"{wo.name}: {wo.nx}x{wo.ny}x{wo.nz}, {wo.nparticles} spheres"
+                                   + (", walls" if wo.walls else ""),
+                       "value": round(ro["mlups"], 1), "unit": "MLUPS",
+                       "ms_per_step": round(ro["ms_per_step"], 4),
+                       "collide_GBps": rl["achieved"], "collide_frac": rl["frac"],
+                       "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)
+                                              for k, v in ro["phases"].items()}})
+        log(f"[bench] {others[-1]}")
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     line = {
         "metric": METRIC,
@@ -311,6 +328,7 @@ def main():
         "fp64": fp64,
         "accuracy": acc,
         "adjoint": adj,
+        "other_workloads": others or None,
         "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)
                                for k, v in res["phases"].items()},
         "flags": res["flags"],
