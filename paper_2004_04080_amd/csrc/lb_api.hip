@@ -3,11 +3,15 @@
 // Validation runs on the host before any device call. A step is a fixed
 // sequence of kernel launches on the context's stream (no host
 // synchronisation inside lb_step):
+//   [moving, side stream] clear accumulators, unraster, raster, Hertz pairs
 //   density (pull-gather moments)                      -> psi
-//   [spheres] clear accumulators; [moving] unraster, raster, events, Hertz pairs
+//   [moving] wait for the side stream; node events
 //   [spheres] frontier fill + Shan-Chen on solids; [walls] wall fill
 //   collide (SC + EDM + store + moving bounce-back + link momentum exchange)
 //   [moving] integrate; swap buffers and maps
+// The side stream (default priority) lets the latency-bound map update run
+// beside the bandwidth-bound density pass; it is joined through an event
+// before anything reads the new map or the accumulators.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -138,15 +142,17 @@ hipEvent_t ev_get(lb_ctx* c) {
 struct Phase {
   lb_ctx* c;
   int ph;
+  hipStream_t s;
   hipEvent_t a = nullptr;
-  Phase(lb_ctx* ctx, int phase) : c(ctx), ph(phase) {
-    if (c->timing && (a = ev_get(c)) != nullptr) (void)hipEventRecord(a, c->stream);
+  Phase(lb_ctx* ctx, int phase, hipStream_t stream = nullptr)
+      : c(ctx), ph(phase), s(stream ? stream : ctx->stream) {
+    if (c->timing && (a = ev_get(c)) != nullptr) (void)hipEventRecord(a, s);
   }
   ~Phase() {
     if (!a) return;
     hipEvent_t b = ev_get(c);
     if (!b) return;
-    (void)hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, s);
     c->ev_open.push_back({ph, {a, b}});
   }
 };
@@ -440,18 +446,33 @@ int lb_step(lb_ctx* c, int32_t nsteps) {
     }
     void* fin = c->B.f[c->cur];
     void* fout = c->B.f[1 - c->cur];
+    const bool moving = c->moving && c->nparticles > 0;
+    if (moving) {
+      // map update and pair forces on the side stream, beside the density pass
+      if (!c->side) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+      }
+      HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+      HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+      {
+        Phase ph(c, 1, c->side);
+        HIPCHK(c, launch_map_update(c, c->side));
+      }
+      HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+    }
     {
       Phase ph(c, 0);
       HIPCHK(c, launch_density(c, fin));
     }
     const uint16_t* own = owner_now(c);
-    if (c->nparticles > 0) {
-      HIPCHK(c, launch_clear_accumulators(c));
-      if (c->moving) {
-        Phase ph(c, 1);
-        HIPCHK(c, launch_step_particles_pre(c));
-        own = static_cast<const uint16_t*>(c->B.owner[1 - c->own_old]);
-      }
+    if (c->nparticles > 0 && !moving) HIPCHK(c, launch_clear_accumulators(c));
+    if (moving) {
+      HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+      Phase ph(c, 1);
+      HIPCHK(c, launch_events(c));
+      own = static_cast<const uint16_t*>(c->B.owner[1 - c->own_old]);
     }
     if (c->nparticles > 0 || c->P.walls) {
       Phase ph(c, 2);
@@ -711,8 +732,12 @@ int lb_timing_read(lb_ctx* c, double ms[LB_NPHASE], int64_t count[LB_NPHASE]) {
 void lb_free(lb_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->side) (void)hipStreamSynchronize(c->side);
   harvest(c, false);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
 }
 

@@ -56,6 +56,10 @@ struct lb_ctx {
   lb_sizes req;
   lb_buffers B;
   hipStream_t stream = nullptr;
+  // second stream for the map update and pair forces of moving spheres, which
+  // overlap the density pass (default priority; joined before the node events)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   lbh::Geometry geo;
   lbh::WorkLayout wl;
   lbh::AdjLayout al;
@@ -104,7 +108,8 @@ hipError_t launch_owner_to_int(lb_ctx* c, const uint16_t* owner, uint32_t first,
 
 // particles
 hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner);   // walls + all spheres at x
-hipError_t launch_step_particles_pre(lb_ctx* c);  // unraster, raster, events, pairs, fill
+hipError_t launch_map_update(lb_ctx* c, hipStream_t s);  // clear, unraster, raster, pairs
+hipError_t launch_events(lb_ctx* c);                     // node creation / destruction
 hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces);
 hipError_t launch_integrate(lb_ctx* c);
 hipError_t launch_clear_accumulators(lb_ctx* c);

@@ -639,22 +639,19 @@ hipError_t launch_clear_accumulators(lb_ctx* c) {
   return hipMemsetAsync(pacc(c), 0, size_t(c->nparticles) * ASTRIDE * sizeof(double), c->stream);
 }
 
-hipError_t launch_step_particles_pre(lb_ctx* c) {
+// On stream s: clear the per-step sphere accumulators, move the spheres in
+// the map (clear their nodes of two steps back, claim those at the current
+// centre) and sum the Hertz pair forces through the cell list. Independent
+// of the populations, so it can run beside the density pass.
+hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   uint16_t* own_new = static_cast<uint16_t*>(c->B.owner[1 - c->own_old]);
   const uint16_t* own_old = static_cast<const uint16_t*>(c->B.owner[c->own_old]);
   const PArgs a = pargs(c, own_new, own_old);
   const dim3 gp(c->nparticles), bp(PBLOCK);
-  hipLaunchKernelGGL(k_unraster, gp, bp, 0, c->stream, a, int(PS_XRB));
-  hipLaunchKernelGGL(k_raster, gp, bp, 0, c->stream, a, int(PS_X));
-  const dim3 gn((c->geo.N + PBLOCK - 1) / PBLOCK);
-  const bool two = c->geo.ncomp == 2;
-  if (c->geo.prec == LB_FP64) {
-    if (two) hipLaunchKernelGGL((k_events<double, 2>), gn, bp, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_events<double, 1>), gn, bp, 0, c->stream, a);
-  } else {
-    if (two) hipLaunchKernelGGL((k_events<float, 2>), gn, bp, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_events<float, 1>), gn, bp, 0, c->stream, a);
-  }
+  hipError_t e0 = hipMemsetAsync(pacc(c), 0, size_t(c->nparticles) * ASTRIDE * sizeof(double), s);
+  if (e0 != hipSuccess) return e0;
+  hipLaunchKernelGGL(k_unraster, gp, bp, 0, s, a, int(PS_XRB));
+  hipLaunchKernelGGL(k_raster, gp, bp, 0, s, a, int(PS_X));
   // Hertz pairs through the cell list
   CellArgs ca;
   ca.ps = pstate(c);
@@ -676,14 +673,32 @@ hipError_t launch_step_particles_pre(lb_ctx* c) {
   ca.walls = c->P.walls;
   ca.zlo = 0.5;
   ca.zhi = c->geo.nz - 1.5;
-  hipError_t e = hipMemsetAsync(ca.count, 0, size_t(ncell) * sizeof(int32_t), c->stream);
+  hipError_t e = hipMemsetAsync(ca.count, 0, size_t(ncell) * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
   const dim3 gt((c->nparticles + PBLOCK - 1) / PBLOCK);
-  hipLaunchKernelGGL(k_cell_count, gt, bp, 0, c->stream, ca);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, c->stream, ca.count, ca.start, ncell);
-  hipLaunchKernelGGL(k_cell_fill, gt, bp, 0, c->stream, ca);
-  hipLaunchKernelGGL(k_cell_sort, dim3((ncell + PBLOCK - 1) / PBLOCK), bp, 0, c->stream, ca, ncell);
-  hipLaunchKernelGGL(k_pairs, gt, bp, 0, c->stream, ca);
+  hipLaunchKernelGGL(k_cell_count, gt, bp, 0, s, ca);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ca.count, ca.start, ncell);
+  hipLaunchKernelGGL(k_cell_fill, gt, bp, 0, s, ca);
+  hipLaunchKernelGGL(k_cell_sort, dim3((ncell + PBLOCK - 1) / PBLOCK), bp, 0, s, ca, ncell);
+  hipLaunchKernelGGL(k_pairs, gt, bp, 0, s, ca);
+  return hipGetLastError();
+}
+
+// Node creation and destruction between the two maps (after the density pass
+// and the map update).
+hipError_t launch_events(lb_ctx* c) {
+  uint16_t* own_new = static_cast<uint16_t*>(c->B.owner[1 - c->own_old]);
+  const uint16_t* own_old = static_cast<const uint16_t*>(c->B.owner[c->own_old]);
+  const PArgs a = pargs(c, own_new, own_old);
+  const dim3 gn((c->geo.N + PBLOCK - 1) / PBLOCK), bp(PBLOCK);
+  const bool two = c->geo.ncomp == 2;
+  if (c->geo.prec == LB_FP64) {
+    if (two) hipLaunchKernelGGL((k_events<double, 2>), gn, bp, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_events<double, 1>), gn, bp, 0, c->stream, a);
+  } else {
+    if (two) hipLaunchKernelGGL((k_events<float, 2>), gn, bp, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_events<float, 1>), gn, bp, 0, c->stream, a);
+  }
   return hipGetLastError();
 }
 
