@@ -226,6 +226,22 @@ int lb_loss(struct lb_ctx* ctx, double* L, double* dL_dpsiA, double* dL_dpsiB);
 int lb_backward(struct lb_ctx* ctx, const double* dL_dpsiA, const double* dL_dpsiB,
                 double* dL_drhoA0, double* dL_dG, double dL_dg[3]);
 
+/* Restart snapshot of the whole evolving state (the paper's restart files,
+ * input directives of App. A): the populations as stored (storage precision,
+ * pull form), both owner maps and the sphere records, behind a small header
+ * (box, components, precision, walls, sphere count, step). The blob is
+ * opaque, host memory owned by the caller; lb_state_bytes gives its size.
+ * lb_get_state synchronises and copies the state out. lb_set_state
+ * synchronises and replaces the state of a context created with the same
+ * box, components, precision and walls and at least as many sphere slots;
+ * the adjoint recording restarts empty. Errors: LB_E_ARG (NULL, short
+ * buffer, bad header), LB_E_SHAPE (blob of another configuration),
+ * LB_E_CAPACITY (more spheres than max_particles), LB_E_HIP. Populations that
+ * are not finite are accepted and reported by lb_observables (flags bit 1). */
+int lb_state_bytes(const struct lb_ctx* ctx, size_t* bytes);
+int lb_get_state(struct lb_ctx* ctx, void* blob, size_t bytes);
+int lb_set_state(struct lb_ctx* ctx, const void* blob, size_t bytes);
+
 /* Wait for all work queued by the context. */
 int lb_sync(struct lb_ctx* ctx);
 

@@ -27,7 +27,7 @@ EXPORTED = [
     "lb_add_particles", "lb_step", "lb_observables", "lb_get_fields", "lb_get_psi",
     "lb_get_populations", "lb_set_populations", "lb_get_owner", "lb_get_particles",
     "lb_set_particles", "lb_num_particles", "lb_loss", "lb_backward", "lb_sync", "lb_free",
-    "lb_timing", "lb_timing_read",
+    "lb_timing", "lb_timing_read", "lb_state_bytes", "lb_get_state", "lb_set_state",
 ]
 NPHASE = 5
 PHASES = ("density", "spheres", "fill", "collide", "integrate")
@@ -118,6 +118,9 @@ def lib():
     L.lb_free.restype = None
     L.lb_timing.argtypes = [vp, C.c_int]
     L.lb_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+    L.lb_state_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.lb_get_state.argtypes = [vp, vp, C.c_size_t]
+    L.lb_set_state.argtypes = [vp, vp, C.c_size_t]
     _lib = L
     return L
 

@@ -495,6 +495,98 @@ int lb_step(lb_ctx* c, int32_t nsteps) {
   return LB_OK;
 }
 
+namespace {
+struct StateHeader {
+  char magic[8];  // "LBSTATE1"
+  int32_t nx, ny, nz, ncomp, precision, walls, nparticles, reserved;
+  int64_t step;
+  uint64_t f_bytes, owner_bytes, particle_bytes;
+};
+constexpr char kStateMagic[8] = {'L', 'B', 'S', 'T', 'A', 'T', 'E', '1'};
+
+void state_parts(const lb_ctx* c, int np, uint64_t& fb, uint64_t& ob, uint64_t& pb) {
+  fb = c->req.f;
+  ob = c->has_solids ? uint64_t(c->geo.N) * sizeof(uint16_t) : 0;
+  pb = uint64_t(np) * PSTRIDE * sizeof(double);
+}
+}  // namespace
+
+int lb_state_bytes(const lb_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return LB_E_ARG;
+  uint64_t fb, ob, pb;
+  state_parts(c, c->nparticles, fb, ob, pb);
+  *bytes = sizeof(StateHeader) + fb + 2 * ob + pb;
+  return LB_OK;
+}
+
+int lb_get_state(lb_ctx* c, void* blob, size_t bytes) {
+  size_t need = 0;
+  if (!c || !blob || lb_state_bytes(c, &need) != LB_OK) return LB_E_ARG;
+  if (bytes < need) return fail(c, LB_E_ARG, "state buffer too small (see lb_state_bytes)");
+  StateHeader h;
+  std::memcpy(h.magic, kStateMagic, sizeof(h.magic));
+  h.nx = int32_t(c->geo.nx);
+  h.ny = int32_t(c->geo.ny);
+  h.nz = int32_t(c->geo.nz);
+  h.ncomp = c->geo.ncomp;
+  h.precision = c->geo.prec;
+  h.walls = c->P.walls;
+  h.nparticles = c->nparticles;
+  h.reserved = 0;
+  h.step = c->step;
+  state_parts(c, c->nparticles, h.f_bytes, h.owner_bytes, h.particle_bytes);
+  char* out = static_cast<char*>(blob);
+  std::memcpy(out, &h, sizeof(h));
+  out += sizeof(h);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(out, c->B.f[c->cur], h.f_bytes, hipMemcpyDeviceToHost));
+  out += h.f_bytes;
+  if (h.owner_bytes) {
+    HIPCHK(c, hipMemcpy(out, c->B.owner[c->own_old], h.owner_bytes, hipMemcpyDeviceToHost));
+    out += h.owner_bytes;
+    HIPCHK(c, hipMemcpy(out, c->B.owner[1 - c->own_old], h.owner_bytes, hipMemcpyDeviceToHost));
+    out += h.owner_bytes;
+  }
+  if (h.particle_bytes)
+    HIPCHK(c, hipMemcpy(out, pstate(c), h.particle_bytes, hipMemcpyDeviceToHost));
+  return LB_OK;
+}
+
+int lb_set_state(lb_ctx* c, const void* blob, size_t bytes) {
+  if (!c || !blob || bytes < sizeof(StateHeader)) return LB_E_ARG;
+  StateHeader h;
+  std::memcpy(&h, blob, sizeof(h));
+  if (std::memcmp(h.magic, kStateMagic, sizeof(h.magic)) != 0)
+    return fail(c, LB_E_ARG, "not a state blob");
+  if (h.nx != int32_t(c->geo.nx) || h.ny != int32_t(c->geo.ny) || h.nz != int32_t(c->geo.nz) ||
+      h.ncomp != c->geo.ncomp || h.precision != c->geo.prec || h.walls != c->P.walls)
+    return fail(c, LB_E_SHAPE, "state blob of another box, component count, precision or walls");
+  if (h.nparticles < 0 || h.nparticles > c->P.max_particles)
+    return fail(c, LB_E_CAPACITY, "state blob holds more spheres than max_particles");
+  uint64_t fb, ob, pb;
+  state_parts(c, h.nparticles, fb, ob, pb);
+  if (h.f_bytes != fb || h.owner_bytes != ob || h.particle_bytes != pb ||
+      bytes < sizeof(h) + fb + 2 * ob + pb)
+    return fail(c, LB_E_ARG, "state blob sizes do not match this context");
+  const char* in = static_cast<const char*>(blob) + sizeof(h);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->B.f[c->cur], in, fb, hipMemcpyHostToDevice));
+  in += fb;
+  if (ob) {
+    HIPCHK(c, hipMemcpy(c->B.owner[c->own_old], in, ob, hipMemcpyHostToDevice));
+    in += ob;
+    HIPCHK(c, hipMemcpy(c->B.owner[1 - c->own_old], in, ob, hipMemcpyHostToDevice));
+    in += ob;
+  }
+  if (pb) HIPCHK(c, hipMemcpy(pstate(c), in, pb, hipMemcpyHostToDevice));
+  c->nparticles = h.nparticles;
+  c->moving = h.nparticles > 0 && !c->P.particles_fixed;
+  c->step = h.step;
+  c->rec_steps = 0;
+  HIPCHK(c, hipMemset(wptr(c, c->wl.flags), 0, 16 * sizeof(int32_t)));
+  return LB_OK;
+}
+
 int lb_sync(lb_ctx* c) {
   if (!c) return LB_E_ARG;
   HIPCHK(c, hipStreamSynchronize(c->stream));

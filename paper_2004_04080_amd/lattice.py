@@ -255,6 +255,21 @@ class Lattice:
         self._chk(B.lib().lb_set_particles(self._ctx, _dp(a)), "lb_set_particles")
 
     # -- differentiation ---------------------------------------------------------
+    def state(self) -> np.ndarray:
+        """Restart snapshot (lb_get_state) as a host uint8 array."""
+        n = C.c_size_t()
+        self._chk(B.lib().lb_state_bytes(self._ctx, C.byref(n)), "lb_state_bytes")
+        blob = np.empty(n.value, dtype=np.uint8)
+        self._chk(B.lib().lb_get_state(self._ctx, C.c_void_p(blob.ctypes.data), n.value),
+                  "lb_get_state")
+        return blob
+
+    def set_state(self, blob: np.ndarray) -> None:
+        """Replace the state with a snapshot taken by state() (lb_set_state)."""
+        b = np.ascontiguousarray(blob, dtype=np.uint8)
+        self._chk(B.lib().lb_set_state(self._ctx, C.c_void_p(b.ctypes.data), b.nbytes),
+                  "lb_set_state")
+
     def loss(self, seeds: bool = False):
         """L (host float); with seeds=True also dL/dpsi_k as device FP64 tensors."""
         import torch
