@@ -84,6 +84,11 @@ def run_gpu(w, rho, x, precision, steps, warmup, want_roofline, want_fields=Fals
     log(f"[bench] {w.name} {precision}: {steps} steps in {ms:.1f} ms; phases {phases}")
     out = dict(ms_per_step=ms / steps, mlups=w.N * steps / (ms * 1e-3) / 1e6, phases=phases,
                flags=obs.flags, mass=obs.mass.tolist())
+    if want_roofline:
+        lat.domain_size()          # the first call creates the FFT plan
+        t = time.time()
+        L, _ = lat.domain_size()
+        out["domain_size"] = {"L": round(L, 4), "ms": round((time.time() - t) * 1e3, 2)}
     if want_roofline or want_fields:
         own = lat.owner()
         if want_roofline:
@@ -331,6 +336,7 @@ def main():
         "other_workloads": others or None,
         "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)
                                for k, v in res["phases"].items()},
+        "domain_size": res.get("domain_size"),
         "flags": res["flags"],
     }
     print(json.dumps(line), flush=True)

@@ -242,6 +242,25 @@ int lb_state_bytes(const struct lb_ctx* ctx, size_t* bytes);
 int lb_get_state(struct lb_ctx* ctx, void* blob, size_t bytes);
 int lb_set_state(struct lb_ctx* ctx, const void* blob, size_t bytes);
 
+/* Average domain size of the phase field (Sec. 4, Eq. Cluster_L_eq):
+ * L = 2 pi sum_s S(s) / sum_s k_s S(s) over the shells s = 1 .. min(L)/2 of
+ * the structure factor S(k) = |phi'(k)|^2 / N of phi' = phi - <phi>,
+ * phi = (rho_A - rho_B) / (rho_A + rho_B) on the fluid nodes of the current
+ * state (0 on solids). Shell s holds the wave vectors k_d = 2 pi m_d / L_d
+ * with round(|k| / dk) = s, dk = 2 pi / min(nx, ny, nz); S(s) is their mean.
+ * Two components only. The transform runs in FP64 on the context's stream.
+ * lb_domain_workspace gives the device workspace size in bytes and the shell
+ * count (min(L)/2 + 1, shell 0 included); it creates the FFT plan on first
+ * use (the only allocation, made by the FFT library; released by lb_free).
+ * lb_domain_size takes a caller-owned device workspace of that size, writes
+ * L to the host (NaN when phi' vanishes) and, unless S is NULL, the shell
+ * means S(0..nshell-1) to a host array of nshell doubles. Synchronises.
+ * Errors: LB_E_ARG (NULL, small workspace or array), LB_E_STATE (one
+ * component), LB_E_HIP. */
+int lb_domain_workspace(struct lb_ctx* ctx, size_t* bytes, int32_t* nshell);
+int lb_domain_size(struct lb_ctx* ctx, void* work, size_t work_bytes, double* L, double* S,
+                   int32_t nshell);
+
 /* Wait for all work queued by the context. */
 int lb_sync(struct lb_ctx* ctx);
 

@@ -11,11 +11,16 @@ Readings (where the paper leaves the discrete form open):
   on solid nodes.
 * Wave vectors are k_d = 2 pi m_d / L_d with integer m_d of the discrete
   Fourier transform (|m_d| <= L_d / 2). Shells have width dk = 2 pi / min(L)
-  and shell s collects the modes with round(|k| / dk) = s; the integrals run
-  over the fully populated shells 1 <= s <= min(L) // 2, as sums with the
-  shell means S(s) = mean of |phi'(k)|^2 / N over the modes of shell s.
+  and shell s collects the modes with round(|k| / dk) = s, halves rounded
+  up; the integrals run over the fully populated shells 1 <= s <= min(L) // 2,
+  as sums with the shell means S(s) = mean of |phi'(k)|^2 / N over the modes
+  of shell s.
+* In boxes of unequal sides |k| / dk can be exactly half-integral, so the
+  rounding is decided in integers (see shells), not in floating point.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -31,15 +36,27 @@ def order_parameter(rho: np.ndarray, fluid: np.ndarray) -> np.ndarray:
 
 
 def shells(shape):
-    """(shell index of every mode [nz][ny][nx], dk, s_max) for a box (nx, ny, nz)."""
+    """(shell index of every mode [nz][ny][nx], dk, s_max) for a box (nx, ny, nz).
+
+    With A = lcm(L_d) and a_d = A / L_d, |k| / dk = Lmin sqrt(Q) / A where
+    Q = sum_d (m_d a_d)^2 is an integer, and round-half-up of |k| / dk is the
+    largest s >= 0 with (2s - 1)^2 A^2 <= 4 Lmin^2 Q, checked in exact
+    integers around a floating-point first guess."""
     nx, ny, nz = shape
-    m = [np.fft.fftfreq(n) * n for n in (nx, ny, nz)]
-    kz, ky, kx = np.meshgrid(2 * np.pi * m[2] / nz, 2 * np.pi * m[1] / ny,
-                             2 * np.pi * m[0] / nx, indexing="ij")
-    k = np.sqrt(kx * kx + ky * ky + kz * kz)
-    dk = 2 * np.pi / min(shape)
-    s = np.floor(k / dk + 0.5).astype(np.int64)
-    return s, dk, min(shape) // 2
+    A = math.lcm(nx, ny, nz)
+    Lmin = min(shape)
+    m = [np.rint(np.fft.fftfreq(n) * n).astype(np.int64) for n in (nx, ny, nz)]
+    mz, my, mx = np.meshgrid(m[2], m[1], m[0], indexing="ij")
+    Q = ((mx * (A // nx)).astype(object) ** 2 + (my * (A // ny)).astype(object) ** 2
+         + (mz * (A // nz)).astype(object) ** 2)
+    s = np.floor(Lmin * np.sqrt(Q.astype(np.float64)) / A + 0.5).astype(np.int64)
+    rhs = 4 * Lmin * Lmin * Q
+    so = s.astype(object)
+    up = (2 * so + 1) ** 2 * (A * A) <= rhs          # s + 1 still satisfies the bound
+    so = np.where(up, so + 1, so)
+    down = (so > 0) & ((2 * so - 1) ** 2 * (A * A) > rhs)
+    so = np.where(down, so - 1, so)
+    return so.astype(np.int64), 2 * np.pi / Lmin, Lmin // 2
 
 
 def structure_factor(phi_prime: np.ndarray, shape):

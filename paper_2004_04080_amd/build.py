@@ -26,7 +26,8 @@ FLAGS = [
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = ["lb_fluid.hip", "lb_particles.hip", "lb_adjoint.hip", "lb_api.hip"]
+SOURCES = ["lb_fluid.hip", "lb_particles.hip", "lb_adjoint.hip", "lb_domain.hip", "lb_api.hip"]
+LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def _compile(src: str, verbose: bool) -> str:
@@ -48,7 +49,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, *LIBS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -830,6 +830,7 @@ void lb_free(lb_ctx* c) {
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->side) (void)hipStreamDestroy(c->side);
+  free_fft(c);
   delete c;
 }
 

@@ -60,6 +60,7 @@ struct lb_ctx {
   // overlap the density pass (default priority; joined before the node events)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  void* fft = nullptr;  // FFT plan of the domain-size measure, made on first use
   lbh::Geometry geo;
   lbh::WorkLayout wl;
   lbh::AdjLayout al;
@@ -119,6 +120,9 @@ hipError_t launch_loss(lb_ctx* c, double* L_dev, double* seedA, double* seedB);
 int backward(lb_ctx* c, const double* seedA, const double* seedB, double* dL_drhoA0,
              double* dL_dG, double* dL_dg);
 int record_checkpoint(lb_ctx* c);
+
+// domain size
+void free_fft(lb_ctx* c);
 
 inline char* wptr(lb_ctx* c, size_t off) { return static_cast<char*>(c->B.work) + off; }
 inline char* aptr(lb_ctx* c, size_t off) { return static_cast<char*>(c->B.adjoint) + off; }

@@ -270,6 +270,21 @@ class Lattice:
         self._chk(B.lib().lb_set_state(self._ctx, C.c_void_p(b.ctypes.data), b.nbytes),
                   "lb_set_state")
 
+    def domain_size(self):
+        """(L, S) of the phase field: the average domain size and the shell
+        means of the structure factor (lb_domain_size)."""
+        import torch
+        n = C.c_size_t()
+        ns = C.c_int32()
+        self._chk(B.lib().lb_domain_workspace(self._ctx, C.byref(n), C.byref(ns)),
+                  "lb_domain_workspace")
+        work = torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+        L = C.c_double()
+        S = np.zeros(ns.value)
+        self._chk(B.lib().lb_domain_size(self._ctx, C.c_void_p(work.data_ptr()), n.value,
+                                         C.byref(L), _dp(S), ns.value), "lb_domain_size")
+        return L.value, S
+
     def loss(self, seeds: bool = False):
         """L (host float); with seeds=True also dL/dpsi_k as device FP64 tensors."""
         import torch

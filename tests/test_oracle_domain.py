@@ -59,3 +59,13 @@ def test_uniform_phase_has_no_structure():
     shape = (8, 8, 8)
     _, S = D.domain_size(_rho_from_phi(np.full(512, 0.3)), np.ones(512, bool), shape)
     assert S.max() < 1e-28   # only the rounding of the mean removal is left
+
+
+def test_half_integral_radius_rounds_up():
+    # 48 x 40 x 36: the mode m = (2, 0, 0) has |k| / dk = 36 * 2 / 48 = 1.5 exactly,
+    # m = (0, 0, 5) has 5 and m = (6, 5, 0) has 36 sqrt(1/64 + 1/64) = 6.36...
+    s, dk, smax = D.shells((48, 40, 36))
+    assert s[0, 0, 2] == 2 and s[0, 0, 46] == 2
+    assert s[5, 0, 0] == 5
+    assert s[0, 5, 6] == 6
+    assert smax == 18 and abs(dk - 2 * np.pi / 36) < 1e-15
