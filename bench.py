@@ -227,6 +227,31 @@ def adjoint_leg():
             "rel_err": float(f"{abs(dG - fd) / abs(fd):.3e}")}
 
 
+def coarsening(name: str, steps: int, every: int) -> dict:
+    """Average domain size L(t) (Eq. Cluster_L_eq) along one FP32 run of a
+    synthetic box, with the wall-clock rate of the run."""
+    import synth
+    from paper_2004_04080_amd import Lattice
+    w = synth.workload(name)
+    lat = Lattice(params_for(w, "fp32"), w.densities())
+    if w.nparticles:
+        lat.add_particles(w.centres())
+    series, t0, done = [], time.time(), 0
+    while done < steps:
+        n = min(every, steps - done)
+        lat.step(n)
+        done += n
+        L, _ = lat.domain_size()
+        series.append([done, round(L, 3)])
+        log(f"[coarsening] {w.name} step {done}: L = {L:.3f}")
+    dt = time.time() - t0
+    obs = lat.observables(raise_on_flag=False)
+    lat.close()
+    return {"coarsening": series, "workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz}, "
+            f"{w.nparticles} spheres R={w.radius} ({100 * synth.sphere_fraction(w):.1f}% solid)",
+            "steps": steps, "seconds": round(dt, 1), "flags": obs.flags}
+
+
 def copy_probe(gib: float, reps: int = 5) -> dict:
     """A plain device-to-device copy of known size: the measured copy bandwidth,
     and the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -265,7 +290,14 @@ def main():
                          "one and reported under other_workloads (FP32, same step counts)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB and report it")
+    ap.add_argument("--coarsening", type=int, default=0,
+                    help="only run this many steps of --workload (FP32) and report the "
+                         "average domain size every --every steps")
+    ap.add_argument("--every", type=int, default=1000)
     args = ap.parse_args()
+    if args.coarsening > 0:
+        print(json.dumps(coarsening(args.workload, args.coarsening, args.every)), flush=True)
+        return
     if args.copy_probe > 0:
         print(json.dumps(copy_probe(args.copy_probe)), flush=True)
         return

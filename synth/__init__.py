@@ -194,6 +194,12 @@ def workload(name: str) -> Workload:
     if name == "T":
         return Workload("T", 512, 512, 512, nparticles=32000, radius=5.5, steps=200, seed=s + 6,
                         notes="512^3 two fluids plus 32,000 spheres R=5.5")
+    if name == "B20":
+        return Workload("B20", 256, 256, 256, nparticles=4815, radius=5.5, steps=20000,
+                        seed=s + 8, notes="256^3 two fluids plus 20% solids (R=5.5), coarsening")
+    if name == "B0":
+        return Workload("B0", 256, 256, 256, steps=20000, seed=s + 8,
+                        notes="256^3 two fluids without spheres, coarsening")
     if name == "MT0":
         return Workload("MT0", 512, 512, 512, steps=200, seed=s + 7,
                         notes="512^3 two fluids, no spheres")
