@@ -83,6 +83,20 @@ typedef struct lb_params {
   int32_t checkpoint_every; /* > 0: lb_step records a checkpoint every that many
                                steps so that lb_backward can run (see there)         */
   int32_t max_record_steps; /* number of steps lb_step may record (with checkpoints) */
+  /* Janus wetting of the spheres (Sec. 4, benchmark input "force shanchen
+   * angle/particel"): on a frontier node at angle theta (degrees) from the
+   * sphere's body x axis, zeta of Eq. soliddens is +janus_zeta[0] S(theta) for
+   * component A and -janus_zeta[1] S(theta) for B, S = 2t^2(3 - 2t) - 1 with
+   * t = clamp((janus_theta0 + janus_width/2 - theta) / janus_width, 0, 1).
+   * janus = 0 keeps the constant zeta[k]; walls always use zeta[k].        */
+  int32_t janus;
+  double  janus_theta0, janus_width, janus_zeta[2];
+  /* Lubrication between spheres (Eq. libric), on when lub_mu > 0: for a gap
+   * h = |r_ij| - 2R below lub_hn, F_i = -6 pi lub_mu R^2/4 (1/h - 1/lub_hn)
+   * ((v_i - v_j) . e_ij) e_ij with e_ij = r_ij/|r_ij|, r_ij = x_j - x_i, and h
+   * held at lub_hcap below it (benchmark input: 0.1, 0.67, 0.5). Added to the
+   * pair force; velocities at t - 1/2.                                      */
+  double  lub_mu, lub_hn, lub_hcap;
 } lb_params;
 
 /* Byte sizes of the caller-owned device buffers. */

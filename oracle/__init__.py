@@ -37,6 +37,9 @@ class _Params(C.Structure):
         ("hertz_K", C.c_double), ("hertz_d0", C.c_double), ("hertz_rcap", C.c_double),
         ("zeta", C.c_double * 2), ("rho_fallback", C.c_double * 2),
         ("rotate", C.c_int32), ("particles_fixed", C.c_int32),
+        ("janus", C.c_int32), ("janus_theta0", C.c_double), ("janus_width", C.c_double),
+        ("janus_zeta", C.c_double * 2),
+        ("lub_mu", C.c_double), ("lub_hn", C.c_double), ("lub_hcap", C.c_double),
     ]
 
 
@@ -62,6 +65,13 @@ class Params:
     rho_fallback: Sequence[float] = (1.0, 1.0)
     rotate: bool = True
     particles_fixed: bool = False
+    janus: bool = False
+    janus_theta0: float = 108.0
+    janus_width: float = 10.0
+    janus_zeta: Sequence[float] = (0.1, 0.1)
+    lub_mu: float = 0.0
+    lub_hn: float = 0.67
+    lub_hcap: float = 0.5
 
     @property
     def N(self) -> int:
@@ -88,6 +98,13 @@ class Params:
         p.rho_fallback[:] = list(self.rho_fallback)
         p.rotate = int(self.rotate)
         p.particles_fixed = int(self.particles_fixed)
+        p.janus = int(self.janus)
+        p.janus_theta0 = self.janus_theta0
+        p.janus_width = self.janus_width
+        p.janus_zeta[:] = list(self.janus_zeta)
+        p.lub_mu = self.lub_mu
+        p.lub_hn = self.lub_hn
+        p.lub_hcap = self.lub_hcap
         return p
 
 
@@ -108,8 +125,8 @@ def lib():
         L.lbo_add_particles.argtypes = [vp, C.c_int32, dp, dp, dp, dp]
         L.lbo_step.argtypes = [vp, C.c_int32]
         L.lbo_lattice.argtypes = [ip, dp]
-        for nm in ("lbo_get_f", "lbo_set_f", "lbo_get_rho", "lbo_get_u", "lbo_get_particles",
-                   "lbo_set_particle_state", "lbo_observables"):
+        for nm in ("lbo_get_f", "lbo_set_f", "lbo_get_rho", "lbo_get_psi", "lbo_get_u",
+                   "lbo_get_particles", "lbo_set_particle_state", "lbo_observables"):
             getattr(L, nm).argtypes = [vp, dp]
         L.lbo_get_owner.argtypes = [vp, ip]
         L.lbo_set_owner.argtypes = [vp, ip]
@@ -193,6 +210,13 @@ class Oracle:
     def rho(self) -> np.ndarray:
         out = np.empty((self.params.ncomp, self.N))
         lib().lbo_get_rho(self._h, _dp(out))
+        return out
+
+    def psi(self) -> np.ndarray:
+        """Pseudo-potential: rho on fluid nodes, virtual densities on the
+        frontier solid nodes, 0 elsewhere."""
+        out = np.empty((self.params.ncomp, self.N))
+        lib().lbo_get_psi(self._h, _dp(out))
         return out
 
     def u(self) -> np.ndarray:

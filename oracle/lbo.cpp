@@ -245,10 +245,27 @@ struct Sim {
         for (int a = 0; a < 3; ++a) d[a] = minimg(parts[q].x[a] - parts[p].x[a], L[a]);
         double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double mag = hertz_mag(r);
-        if (mag == 0.0) continue;
-        for (int a = 0; a < 3; ++a) {
-          parts[p].FH[a] -= mag * d[a] / r;
-          parts[q].FH[a] += mag * d[a] / r;
+        if (mag != 0.0)
+          for (int a = 0; a < 3; ++a) {
+            parts[p].FH[a] -= mag * d[a] / r;
+            parts[q].FH[a] += mag * d[a] / r;
+          }
+        // Lubrication (Eq. libric). READING: the printed scalar acts along the
+        // unit vector r_pq / |r_pq| (r_pq = x_q - x_p), with the coefficient
+        // lub_mu in place of the viscosity and the gap held at lub_hcap below
+        // it; velocities at t - 1/2 (the latest known). It resists the
+        // relative motion along the line of centres.
+        const double h = r - 2.0 * P.radius;
+        if (P.lub_mu > 0.0 && h < P.lub_hn) {
+          const double he = std::max(h, P.lub_hcap);
+          double vn = 0.0;
+          for (int a = 0; a < 3; ++a) vn += (parts[p].v[a] - parts[q].v[a]) * d[a] / r;
+          const double fl = -6.0 * M_PI * P.lub_mu * 0.25 * P.radius * P.radius *
+                            (1.0 / he - 1.0 / P.lub_hn) * vn;
+          for (int a = 0; a < 3; ++a) {
+            parts[p].FH[a] += fl * d[a] / r;
+            parts[q].FH[a] -= fl * d[a] / r;
+          }
         }
       }
     // READING: with walls, each wall plane (halfway between the wall layer and
@@ -357,9 +374,35 @@ struct Sim {
           int64_t m = nb[n * Q + i];
           if (M[m] == 0) s += rho[int64_t(k) * N + m] * WT[i];
         }
-        rt[int64_t(k) * N + n] = (1.0 + P.zeta[k]) * s / wsum;
+        rt[int64_t(k) * N + n] = (1.0 + zeta_at(M, n, k)) * s / wsum;
       }
     }
+  }
+
+  // Wetting constant of a solid node (Eq. soliddens). READING (Janus
+  // particles, benchmark input "force shanchen angle/particel"): on a sphere
+  // node at angle theta from the sphere's body x axis (first column of R(q)),
+  // zeta_A = +janus_zeta[0] S(theta) and zeta_B = -janus_zeta[1] S(theta),
+  // S = 2 t^2 (3 - 2t) - 1 with t = clamp((theta0 + width/2 - theta) / width,
+  // 0, 1): +1 on the cap around the axis, -1 on the opposite side, a smooth
+  // step across the band of the given width around theta0.
+  double zeta_at(const std::vector<int>& M, int64_t n, int k) const {
+    if (!P.janus || M[n] <= 0) return P.zeta[k];
+    const Particle& pp = parts[M[n] - 1];
+    const double* q = pp.q;
+    const double ax[3] = {q[0] * q[0] + q[1] * q[1] - q[2] * q[2] - q[3] * q[3],
+                          2 * (q[1] * q[2] + q[0] * q[3]), 2 * (q[1] * q[3] - q[0] * q[2])};
+    double d[3];
+    sep(n, pp.x, d);
+    const double dn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double an = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    double c = (d[0] * ax[0] + d[1] * ax[1] + d[2] * ax[2]) / (dn * an);
+    c = std::min(1.0, std::max(-1.0, c));
+    const double theta = std::acos(c) * 180.0 / M_PI;
+    double t = (P.janus_theta0 + 0.5 * P.janus_width - theta) / P.janus_width;
+    t = std::min(1.0, std::max(0.0, t));
+    const double S = 2.0 * t * t * (3.0 - 2.0 * t) - 1.0;
+    return k == 0 ? P.janus_zeta[0] * S : -P.janus_zeta[1] * S;
   }
 
   bool frontier(const std::vector<int>& M, int64_t n) const {
@@ -729,6 +772,9 @@ bool valid(const lbo_params* p) {
   for (int k = 0; k < p->ncomp; ++k)
     if (!(p->tau[k] > 0.5)) return false;
   if (p->walls && p->nz < 3) return false;
+  if (p->janus && !(p->janus_width > 0.0)) return false;
+  if (p->lub_mu < 0.0 || (p->lub_mu > 0.0 && !(p->lub_hn > p->lub_hcap && p->lub_hcap > 0.0)))
+    return false;
   return true;
 }
 
@@ -787,6 +833,14 @@ void lbo_get_rho(const void* s, double* out) {
   std::vector<double> rho, j, u;
   S->moments(S->own, rho, j, u);
   std::memcpy(out, rho.data(), rho.size() * sizeof(double));
+}
+
+void lbo_get_psi(const void* s, double* out) {
+  auto* S = const_cast<Sim<double>*>(static_cast<const Sim<double>*>(s));
+  std::vector<double> rho, j, u, rt;
+  S->moments(S->own, rho, j, u);
+  S->fill(S->own, rho, rt);
+  std::memcpy(out, rt.data(), rt.size() * sizeof(double));
 }
 
 void lbo_get_u(const void* s, double* out) {

@@ -50,6 +50,18 @@ typedef struct lbo_params {
   int32_t rotate;           /* integrate the rotational degrees of freedom      */
   int32_t particles_fixed;  /* spheres are static obstacles: no map updates,
                                no pair forces, no integration                  */
+  /* Janus wetting (Sec. 4, benchmark input): on a sphere's frontier node at
+   * angle theta (degrees) from the sphere's body x axis, zeta_k of Eq.
+   * soliddens is +janus_zeta[0] S(theta) for component A and
+   * -janus_zeta[1] S(theta) for B, with the switching function S going
+   * smoothly from +1 (theta <= theta0 - width/2) to -1 (theta >= theta0 +
+   * width/2). janus = 0 keeps the constant zeta[k]. */
+  int32_t janus;
+  double  janus_theta0, janus_width, janus_zeta[2];
+  /* Lubrication between sphere pairs (Eq. libric), lub_mu > 0 switches it on:
+   * F_i = -6 pi lub_mu R^2/4 (1/h - 1/lub_hn) ((v_i - v_j) . r_ij/|r_ij|) r_ij/|r_ij|
+   * for gaps h = |r_ij| - 2R below lub_hn, with h held at lub_hcap below it. */
+  double  lub_mu, lub_hn, lub_hcap;
 } lbo_params;
 
 /* per-particle record returned by lbo_get_particles, in this order */
@@ -84,6 +96,9 @@ void    lbo_lattice(int32_t* c /* [19][3] */, double* w /* [19] */);
 void    lbo_get_f(const void* s, double* f);
 void    lbo_set_f(void* s, const double* f);
 void    lbo_get_rho(const void* s, double* rho /* [ncomp][N] */);
+/* pseudo-potential of the current state: rho_k on fluid nodes, the virtual
+ * densities of Eq. soliddens on frontier solid nodes, 0 elsewhere */
+void    lbo_get_psi(const void* s, double* psi /* [ncomp][N] */);
 void    lbo_get_u(const void* s, double* u /* [N][3] */);
 void    lbo_get_owner(const void* s, int32_t* owner);
 void    lbo_set_owner(void* s, const int32_t* owner);

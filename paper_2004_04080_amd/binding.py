@@ -45,6 +45,9 @@ class lb_params(C.Structure):
         ("hertz_rcap", C.c_double), ("zeta", C.c_double * 2), ("rho_fallback", C.c_double * 2),
         ("rotate", C.c_int32), ("particles_fixed", C.c_int32), ("checkpoint_every", C.c_int32),
         ("max_record_steps", C.c_int32),
+        ("janus", C.c_int32), ("janus_theta0", C.c_double), ("janus_width", C.c_double),
+        ("janus_zeta", C.c_double * 2),
+        ("lub_mu", C.c_double), ("lub_hn", C.c_double), ("lub_hcap", C.c_double),
     ]
 
 

@@ -513,6 +513,10 @@ int backward(lb_ctx* c, const double* seedA, const double* seedB, double* dA0, d
     c->err = "lb_backward: moving spheres change the map; set particles_fixed";
     return LB_E_STATE;
   }
+  if (P.janus && c->nparticles > 0) {
+    c->err = "lb_backward: Janus wetting is not differentiated";
+    return LB_E_STATE;
+  }
   if (g.ncomp == 2 && P.tau[0] != P.tau[1]) {
     c->err = "lb_backward: needs equal relaxation times";
     return LB_E_STATE;

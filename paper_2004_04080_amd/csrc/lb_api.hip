@@ -67,6 +67,18 @@ int validate(const lb_params* p, std::string& why) {
       return LB_E_ARG;
     }
   if (p->precision != LB_FP32 && p->precision != LB_FP64) { why = "bad precision"; return LB_E_ARG; }
+  if (p->janus != 0 && p->janus != 1) { why = "janus must be 0 or 1"; return LB_E_ARG; }
+  if (p->janus && !(p->janus_width > 0.0 && is_finite(p->janus_width) &&
+                    is_finite(p->janus_theta0) && is_finite(p->janus_zeta[0]) &&
+                    is_finite(p->janus_zeta[1]))) {
+    why = "janus needs a finite width > 0, angle and constants";
+    return LB_E_ARG;
+  }
+  if (!(p->lub_mu >= 0.0) || !is_finite(p->lub_mu) ||
+      (p->lub_mu > 0.0 && !(p->lub_hcap > 0.0 && p->lub_hn > p->lub_hcap && is_finite(p->lub_hn)))) {
+    why = "lubrication needs lub_mu >= 0 and 0 < lub_hcap < lub_hn";
+    return LB_E_ARG;
+  }
   // kernels address one population plane [k][i][*] with 32-bit byte offsets
   if (N * (p->precision == LB_FP64 ? 8u : 4u) > 0xFFFFFFFFull) {
     why = "one population plane (nodes x element size) exceeds 4 GiB";

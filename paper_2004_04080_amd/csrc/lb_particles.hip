@@ -67,6 +67,8 @@ struct PArgs {
   int ncomp;
   int walls;
   int np;
+  int janus;
+  double janus_theta0, janus_width, janus_zeta[2];
 };
 
 // Sum NV doubles over the workgroup; thread 0 gets the result.
@@ -345,10 +347,33 @@ __global__ void __launch_bounds__(PBLOCK) k_fill_nodes(PArgs a) {
         sk[k] = W1 * double(s1) + W2 * double(s2);
         for (int d = 0; d < 3; ++d) gk[k][d] = W1 * double(g1[d]) + W2 * double(g2[d]);
       }
+      double zeta[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) zeta[k] = a.zeta[k];
+      if (a.janus) {
+        // Janus wetting: angle from the sphere's body x axis, smooth switch
+        const double* P = a.ps + size_t(o - 1) * PSTRIDE;
+        const double q0 = P[PS_Q], q1 = P[PS_Q + 1], q2 = P[PS_Q + 2], q3 = P[PS_Q + 3];
+        const double ax[3] = {q0 * q0 + q1 * q1 - q2 * q2 - q3 * q3, 2 * (q1 * q2 + q0 * q3),
+                              2 * (q1 * q3 - q0 * q2)};
+        const double d[3] = {min_image(double(x) - P[PS_X], a.L[0]),
+                             min_image(double(y) - P[PS_X + 1], a.L[1]),
+                             min_image(double(z) - P[PS_X + 2], a.L[2])};
+        const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double an = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+        double cth = (d[0] * ax[0] + d[1] * ax[1] + d[2] * ax[2]) / (dn * an);
+        cth = fmin(1.0, fmax(-1.0, cth));
+        const double theta = acos(cth) * (180.0 / M_PI);
+        double t = (a.janus_theta0 + 0.5 * a.janus_width - theta) / a.janus_width;
+        t = fmin(1.0, fmax(0.0, t));
+        const double S = 2.0 * t * t * (3.0 - 2.0 * t) - 1.0;
+        zeta[0] = a.janus_zeta[0] * S;
+        if (NC == 2) zeta[NC - 1] = -a.janus_zeta[1] * S;
+      }
       double dv[NC];
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
-        dv[k] = a.zeta[k] * a.rho0[k] + (1.0 + a.zeta[k]) * sk[k] / wsum;
+        dv[k] = zeta[k] * a.rho0[k] + (1.0 + zeta[k]) * sk[k] / wsum;
         psi[size_t(k) * N + n] = real(dv[k]);
       }
       if (NC == 2 && a.acc) {
@@ -391,6 +416,7 @@ struct CellArgs {
   double K, d0, rcap;
   int walls;
   double zlo, zhi;
+  double R, lub_mu, lub_hn, lub_hcap;
 };
 
 // cell of one coordinate, clamped to [0, nc) in floating point before the
@@ -503,8 +529,20 @@ __global__ void k_pairs(CellArgs a) {
                                min_image(xq[2] - xp[2], a.L[2])};
           const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
           const double mag = hertz_mag(r, a.K, a.d0, a.rcap);
-          if (mag == 0.0) continue;
-          for (int e = 0; e < 3; ++e) F[e] -= mag * d[e] / r;
+          if (mag != 0.0)
+            for (int e = 0; e < 3; ++e) F[e] -= mag * d[e] / r;
+          // lubrication (Eq. libric) along the line of centres
+          const double h = r - 2.0 * a.R;
+          if (a.lub_mu > 0.0 && h < a.lub_hn) {
+            const double he = fmax(h, a.lub_hcap);
+            const double* vp = xp + PS_V;
+            const double* vq = xq + PS_V;
+            double vn = 0.0;
+            for (int e = 0; e < 3; ++e) vn += (vp[e] - vq[e]) * d[e] / r;
+            const double fl = -6.0 * M_PI * a.lub_mu * 0.25 * a.R * a.R *
+                              (1.0 / he - 1.0 / a.lub_hn) * vn;
+            for (int e = 0; e < 3; ++e) F[e] += fl * d[e] / r;
+          }
         }
       }
   if (a.walls) {  // mirror image across each wall plane
@@ -622,6 +660,11 @@ static PArgs pargs(lb_ctx* c, uint16_t* own_new, const uint16_t* own_old) {
   a.Gs = c->P.G * c->P.sc_norm;
   a.walls = c->P.walls;
   a.np = c->nparticles;
+  a.janus = c->P.janus;
+  a.janus_theta0 = c->P.janus_theta0;
+  a.janus_width = c->P.janus_width;
+  a.janus_zeta[0] = c->P.janus_zeta[0];
+  a.janus_zeta[1] = c->P.janus_zeta[1];
   return a;
 }
 
@@ -673,6 +716,10 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   ca.walls = c->P.walls;
   ca.zlo = 0.5;
   ca.zhi = c->geo.nz - 1.5;
+  ca.R = c->P.radius;
+  ca.lub_mu = c->P.lub_mu;
+  ca.lub_hn = c->P.lub_hn;
+  ca.lub_hcap = c->P.lub_hcap;
   hipError_t e = hipMemsetAsync(ca.count, 0, size_t(ncell) * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
   const dim3 gt((c->nparticles + PBLOCK - 1) / PBLOCK);

@@ -43,6 +43,13 @@ class Params:
     particles_fixed: bool = False
     checkpoint_every: int = 0
     max_record_steps: int = 0
+    janus: bool = False
+    janus_theta0: float = 108.0
+    janus_width: float = 10.0
+    janus_zeta: Sequence[float] = (0.1, 0.1)
+    lub_mu: float = 0.0
+    lub_hn: float = 0.67
+    lub_hcap: float = 0.5
 
     @property
     def N(self) -> int:
@@ -75,6 +82,13 @@ class Params:
         p.particles_fixed = int(self.particles_fixed)
         p.checkpoint_every = self.checkpoint_every
         p.max_record_steps = self.max_record_steps
+        p.janus = int(self.janus)
+        p.janus_theta0 = self.janus_theta0
+        p.janus_width = self.janus_width
+        p.janus_zeta[:] = [float(v) for v in self.janus_zeta]
+        p.lub_mu = self.lub_mu
+        p.lub_hn = self.lub_hn
+        p.lub_hcap = self.lub_hcap
         return p
 
 

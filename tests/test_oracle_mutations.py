@@ -30,7 +30,7 @@ MUTATIONS = {
     "half_step_average_dropped": ("sf.add(0.5 * (pp.Fprev[a] + Fl[a]));", "sf.add(Fl[a]);"),
     "moving_wall_factor": ("T corr = 2.0 * WT[i] * rho[int64_t(k) * N + n] * ucw / CS2;",
                            "T corr = WT[i] * rho[int64_t(k) * N + n] * ucw / CS2;"),
-    "wetting_prefactor_dropped": ("rt[int64_t(k) * N + n] = (1.0 + P.zeta[k]) * s / wsum;",
+    "wetting_prefactor_dropped": ("rt[int64_t(k) * N + n] = (1.0 + zeta_at(M, n, k)) * s / wsum;",
                                   "rt[int64_t(k) * N + n] = s / wsum;"),
     "creation_momentum_sign": ("pp.Fc[a].add(-Pm[a]);", "pp.Fc[a].add(Pm[a]);"),
     "destruction_torque_cross": ("cross(d, J, tq);", "cross(J, d, tq);"),
