@@ -97,6 +97,19 @@ typedef struct lb_params {
    * held at lub_hcap below it (benchmark input: 0.1, 0.67, 0.5). Added to the
    * pair force; velocities at t - 1/2.                                      */
   double  lub_mu, lub_hn, lub_hcap;
+  /* Type of the two z faces when walls = 1, [0] at z = 0 and [1] at z = nz-1
+   * (Sec. 2.2, Eq. bb, bbv, bbp; input directive "bound open ... type"):
+   *   0 moving wall, Eq. bbv with the local density and wall_u_lo/hi;
+   *   1 pressure: anti-bounce-back Eq. bbp with the density wall_rho[f][k]
+   *     and the mixture velocity extrapolated from the fluid;
+   *   2 velocity: Eq. bbv with wall_u_lo/hi and the density extrapolated;
+   *   3 equilibrium: f_eq(wall_rho[f][k], wall_u) enters through the face.
+   * Extrapolation: X_w = X(r_b) + (X(r_b) - X(r_b')) / 2, r_b the fluid node
+   * next to the face and r_b' the next one inwards (X(r_b) alone when r_b' is
+   * solid). Open faces need nz >= 4; the wall layers keep their virtual
+   * densities (zeta) for the Shan-Chen force.                               */
+  int32_t wall_type[2];
+  double  wall_rho[2][2];
 } lb_params;
 
 /* Byte sizes of the caller-owned device buffers. */

@@ -40,6 +40,7 @@ class _Params(C.Structure):
         ("janus", C.c_int32), ("janus_theta0", C.c_double), ("janus_width", C.c_double),
         ("janus_zeta", C.c_double * 2),
         ("lub_mu", C.c_double), ("lub_hn", C.c_double), ("lub_hcap", C.c_double),
+        ("wall_type", C.c_int32 * 2), ("wall_rho", C.c_double * 4),
     ]
 
 
@@ -72,6 +73,8 @@ class Params:
     lub_mu: float = 0.0
     lub_hn: float = 0.67
     lub_hcap: float = 0.5
+    wall_type: Sequence[int] = (0, 0)
+    wall_rho: Sequence[Sequence[float]] = ((1.0, 1.0), (1.0, 1.0))
 
     @property
     def N(self) -> int:
@@ -105,6 +108,8 @@ class Params:
         p.lub_mu = self.lub_mu
         p.lub_hn = self.lub_hn
         p.lub_hcap = self.lub_hcap
+        p.wall_type[:] = [int(v) for v in self.wall_type]
+        p.wall_rho[:] = [float(v) for face in self.wall_rho for v in face]
         return p
 
 

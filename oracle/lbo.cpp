@@ -405,6 +405,52 @@ struct Sim {
     return k == 0 ? P.janus_zeta[0] * S : -P.janus_zeta[1] * S;
   }
 
+  // Open face (Sec. 2.2): the population that leaves fluid node n along c_i
+  // into the face layer returns along -c_i as
+  //   pressure:    -f*_i + 2 w_i rho_w [1 + (u_w.c_i)^2/(2 cs^4) - u_w^2/(2 cs^2)]  (Eq. bbp)
+  //   velocity:     f*_i - 2 w_i rho_w (u_w.c_i)/cs^2                                (Eq. bbv)
+  //   equilibrium:  f_eq_{-i}(rho_w, u_w)
+  // with the given rho_w (pressure, equilibrium) or u_w (velocity,
+  // equilibrium) and the other one extrapolated from the fluid:
+  // X_w = X(n) + (X(n) - X(n')) / 2, n' the next node inwards along z.
+  // READING: if n' is not fluid, X_w = X(n). The mixture velocity u of S1 is
+  // extrapolated; densities per component. Momentum and mass that cross the
+  // face go into the wall ledgers.
+  void open_face(int face, int64_t n, int i, const std::vector<int>& M, const std::vector<T>& rho,
+                 const std::vector<T>& u, const std::vector<T>& fs, std::vector<T>& refl,
+                 NSum<double>* led_ml, NSum<double>* led_wall) const {
+    const int type = P.wall_type[face];
+    const double* U = face == 0 ? P.wall_u_lo : P.wall_u_hi;
+    const int64_t inner = idx(cx(n), cy(n), cz(n) + (face == 0 ? 1 : -1));
+    const bool ok = M[inner] == 0;
+    T Fl[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < K; ++k) {
+      const T fsi = fs[(int64_t(k) * Q + i) * N + n];
+      T r;
+      if (type == 1) {
+        T uw[3];
+        for (int a = 0; a < 3; ++a)
+          uw[a] = ok ? u[n * 3 + a] + 0.5 * (u[n * 3 + a] - u[inner * 3 + a]) : u[n * 3 + a];
+        const T uc = uw[0] * CV[i][0] + uw[1] * CV[i][1] + uw[2] * CV[i][2];
+        const T uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+        r = -fsi + 2.0 * WT[i] * P.wall_rho[face][k] *
+                       (1.0 + uc * uc / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+      } else if (type == 2) {
+        const T rn = rho[int64_t(k) * N + n];
+        const T rw = ok ? rn + 0.5 * (rn - rho[int64_t(k) * N + inner]) : rn;
+        const double uc = U[0] * CV[i][0] + U[1] * CV[i][1] + U[2] * CV[i][2];
+        r = fsi - 2.0 * WT[i] * rw * uc / CS2;
+      } else {
+        const T Ut[3] = {U[0], U[1], U[2]};
+        r = feq<T>(opposite(i), T(P.wall_rho[face][k]), Ut);
+      }
+      refl[(int64_t(k) * Q + opposite(i)) * N + n] = r;
+      for (int a = 0; a < 3; ++a) Fl[a] += (fsi + r) * double(CV[i][a]);
+      led_ml[k].add(val(r - fsi));
+    }
+    for (int a = 0; a < 3; ++a) led_wall[a].add(val(Fl[a]));
+  }
+
   bool frontier(const std::vector<int>& M, int64_t n) const {
     if (M[n] == 0) return false;
     for (int i = 1; i < Q; ++i)
@@ -598,8 +644,13 @@ struct Sim {
         double uw[3], rw[3] = {0.0, 0.0, 0.0};
         Particle* pp = nullptr;
         if (o < 0) {
-          const double* U = (cz(s) == 0) ? P.wall_u_lo : P.wall_u_hi;
+          const int face = cz(s) == 0 ? 0 : 1;
+          const double* U = face == 0 ? P.wall_u_lo : P.wall_u_hi;
           for (int a = 0; a < 3; ++a) uw[a] = U[a];
+          if (P.wall_type[face] != 0) {
+            open_face(face, n, i, own_new, rho, u, fs, refl, led_ml, led_wall);
+            continue;
+          }
         } else {
           pp = &parts[o - 1];
           double r[3] = {cx(n) + 0.5 * CV[i][0], cy(n) + 0.5 * CV[i][1], cz(n) + 0.5 * CV[i][2]};
@@ -773,6 +824,10 @@ bool valid(const lbo_params* p) {
     if (!(p->tau[k] > 0.5)) return false;
   if (p->walls && p->nz < 3) return false;
   if (p->janus && !(p->janus_width > 0.0)) return false;
+  for (int f = 0; f < 2; ++f) {
+    if (p->wall_type[f] < 0 || p->wall_type[f] > 3) return false;
+    if (p->wall_type[f] != 0 && p->nz < 4) return false;
+  }
   if (p->lub_mu < 0.0 || (p->lub_mu > 0.0 && !(p->lub_hn > p->lub_hcap && p->lub_hcap > 0.0)))
     return false;
   return true;

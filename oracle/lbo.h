@@ -62,6 +62,18 @@ typedef struct lbo_params {
    * F_i = -6 pi lub_mu R^2/4 (1/h - 1/lub_hn) ((v_i - v_j) . r_ij/|r_ij|) r_ij/|r_ij|
    * for gaps h = |r_ij| - 2R below lub_hn, with h held at lub_hcap below it. */
   double  lub_mu, lub_hn, lub_hcap;
+  /* Boundary type of the two z faces (walls = 1), [0] at z = 0, [1] at
+   * z = nz-1 (Sec. 2.2, Eq. bb, bbv, bbp and the input directive "bound open"):
+   *   0 moving wall: Eq. bbv with the local density and wall_u_lo/hi;
+   *   1 pressure (Dirichlet): anti-bounce-back Eq. bbp with the density
+   *     wall_rho[face][k] and the velocity extrapolated from the fluid;
+   *   2 velocity (Neumann): Eq. bbv with wall_u_lo/hi and the density
+   *     extrapolated from the fluid;
+   *   3 equilibrium: f_eq(wall_rho[face][k], wall_u) enters from the face.
+   * Extrapolation to the face: X_w = X(r_b) + (X(r_b) - X(r_b+1)) / 2 with
+   * r_b the fluid node next to the face and r_b+1 the next one inwards. */
+  int32_t wall_type[2];
+  double  wall_rho[2][2];
 } lbo_params;
 
 /* per-particle record returned by lbo_get_particles, in this order */

@@ -48,6 +48,7 @@ class lb_params(C.Structure):
         ("janus", C.c_int32), ("janus_theta0", C.c_double), ("janus_width", C.c_double),
         ("janus_zeta", C.c_double * 2),
         ("lub_mu", C.c_double), ("lub_hn", C.c_double), ("lub_hcap", C.c_double),
+        ("wall_type", C.c_int32 * 2), ("wall_rho", C.c_double * 4),
     ]
 
 

@@ -513,6 +513,10 @@ int backward(lb_ctx* c, const double* seedA, const double* seedB, double* dA0, d
     c->err = "lb_backward: moving spheres change the map; set particles_fixed";
     return LB_E_STATE;
   }
+  if (P.walls && (P.wall_type[0] != 0 || P.wall_type[1] != 0)) {
+    c->err = "lb_backward: open faces are not differentiated";
+    return LB_E_STATE;
+  }
   if (P.janus && c->nparticles > 0) {
     c->err = "lb_backward: Janus wetting is not differentiated";
     return LB_E_STATE;

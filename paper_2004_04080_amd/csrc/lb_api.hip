@@ -68,6 +68,20 @@ int validate(const lb_params* p, std::string& why) {
     }
   if (p->precision != LB_FP32 && p->precision != LB_FP64) { why = "bad precision"; return LB_E_ARG; }
   if (p->janus != 0 && p->janus != 1) { why = "janus must be 0 or 1"; return LB_E_ARG; }
+  for (int f = 0; f < 2; ++f) {
+    const int t = p->wall_type[f];
+    if (t < 0 || t > 3) { why = "wall_type must be 0..3"; return LB_E_ARG; }
+    if (t != 0 && (!p->walls || p->nz < 4)) {
+      why = "open faces need walls = 1 and nz >= 4";
+      return LB_E_ARG;
+    }
+    if (t == 1 || t == 3)
+      for (int k = 0; k < p->ncomp; ++k)
+        if (!(p->wall_rho[f][k] > 0.0) || !is_finite(p->wall_rho[f][k])) {
+          why = "wall_rho must be finite and > 0 on pressure and equilibrium faces";
+          return LB_E_ARG;
+        }
+  }
   if (p->janus && !(p->janus_width > 0.0 && is_finite(p->janus_width) &&
                     is_finite(p->janus_theta0) && is_finite(p->janus_zeta[0]) &&
                     is_finite(p->janus_zeta[1]))) {
@@ -219,6 +233,8 @@ size_t work_layout(const lb_params& p, WorkLayout& wl, int ncell_total) {
   wl.staging_n = 5 * std::min<size_t>(N, size_t(1) << 20);
   wl.staging = off;
   off = align_up(off + wl.staging_n * sizeof(double));
+  wl.ubnd = off;
+  if (has_pressure_face(p)) off = align_up(off + 2 * size_t(p.nx) * p.ny * 3 * sizeof(double));
   wl.total = off;
   return off;
 }
@@ -486,6 +502,7 @@ int lb_step(lb_ctx* c, int32_t nsteps) {
       HIPCHK(c, launch_events(c));
       own = static_cast<const uint16_t*>(c->B.owner[1 - c->own_old]);
     }
+    if (has_pressure_face(c->P)) HIPCHK(c, launch_face_velocity(c, fin));
     if (c->nparticles > 0 || c->P.walls) {
       Phase ph(c, 2);
       if (c->nparticles > 0) HIPCHK(c, launch_fill_particles(c, own, true));

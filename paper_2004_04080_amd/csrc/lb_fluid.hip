@@ -91,6 +91,9 @@ struct CollideArgs {
   double omega;       // relaxation rate when the relaxation times are equal
   int equal_tau;
   double wall_lo[3], wall_hi[3];
+  int wall_type[2];         // 0 moving wall, 1 pressure, 2 velocity, 3 equilibrium
+  double wall_rho[2][2];    // [face][component]
+  const double* ubnd;       // [2][nx*ny][3] mixture velocity one layer inside each face
   double L[3], invL[3];
   uint32_t blocks_per_xcd;  // workgroups per XCD (grid = 8 x blocks_per_xcd)
 };
@@ -148,10 +151,64 @@ __device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, d
 // lv for sphere pid (flushed with atomics when a lane moves on to another
 // sphere). u_w = v + w x (r_w - x_p) with r_w the link midpoint.
 // ---------------------------------------------------------------------------
+// Open face (Sec. 2.2): the population leaving fluid node n along c_i into
+// the face layer returns along -c_i (full values; stored as deviations) as
+//   pressure:     -f*_i + 2 w_i rho_w [1 + (u_w.c_i)^2/(2 cs^4) - u_w^2/(2 cs^2)]  (Eq. bbp)
+//   velocity:      f*_i - 2 w_i rho_w (u_w.c_i)/cs^2                                (Eq. bbv)
+//   equilibrium:   f_eq_{-i}(rho_w, u_w)
+// with the face's density (pressure, equilibrium) or velocity (velocity,
+// equilibrium) and the other extrapolated: X_w = X(n) + (X(n) - X(n'))/2,
+// n' the next node inwards along z (X(n) alone if n' is solid).
+template <typename real, int NC>
+__device__ void open_face(const CollideArgs& a, int face, int i, int j, uint32_t s, uint32_t x,
+                          uint32_t y, uint32_t z, const real fs[NC], const real rho[NC],
+                          const real u[3]) {
+  const uint32_t N = a.N;
+  real* __restrict__ fout = static_cast<real*>(a.fout);
+  const real* __restrict__ psi = static_cast<const real*>(a.psi);
+  const int cx = dir_c(PCX, i), cy = dir_c(PCY, i), cz = dir_c(PCZ, i);
+  const double wi = (cx * cx + cy * cy + cz * cz == 1) ? W1 : W2;
+  const uint32_t plane = a.nx * a.ny;
+  const uint32_t n = x + a.nx * (y + a.ny * z);
+  const uint32_t nin = face == 0 ? n + plane : n - plane;
+  const bool ok = a.owner[nin] == 0;
+  const int type = a.wall_type[face];
+  const double* U = face == 0 ? a.wall_lo : a.wall_hi;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const double w0 = wi * a.rho0[k];
+    const double f = double(fs[k]) + w0;  // full post-collision value
+    double r;
+    if (type == 1) {
+      const double* ui = a.ubnd + (size_t(face) * plane + (x + a.nx * y)) * 3;
+      double uw[3];
+      for (int d = 0; d < 3; ++d) {
+        const double un = double(u[d]);
+        uw[d] = ok ? un + 0.5 * (un - ui[d]) : un;
+      }
+      const double uc = uw[0] * cx + uw[1] * cy + uw[2] * cz;
+      const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+      r = -f + 2.0 * wi * a.wall_rho[face][k] * (1.0 + 4.5 * uc * uc - 1.5 * uu);
+    } else if (type == 2) {
+      const double rn = double(rho[k]);
+      const double rin = a.rho0[k] + double(psi[size_t(k) * N + nin]);
+      const double rw = ok ? rn + 0.5 * (rn - rin) : rn;
+      r = f - 6.0 * wi * rw * (U[0] * cx + U[1] * cy + U[2] * cz);
+    } else {
+      // f_eq along -c_i
+      const double uc = -(U[0] * cx + U[1] * cy + U[2] * cz);
+      const double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+      r = wi * a.wall_rho[face][k] * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * uu);
+    }
+    st32(fout + (size_t(k) * Q + j) * N, s, real(r - w0));
+  }
+}
+
 template <typename real, int NC>
 __device__ __forceinline__ void link_one(const CollideArgs& a, int i, uint16_t o, uint32_t x,
                                          uint32_t y, uint32_t z, const real fs[NC],
-                                         const real rho[NC], int& pid, double lv[7]) {
+                                         const real rho[NC], const real u[3], int& pid,
+                                         double lv[7]) {
   const uint32_t N = a.N;
   real* __restrict__ fout = static_cast<real*>(a.fout);
   const int cx = dir_c(PCX, i), cy = dir_c(PCY, i), cz = dir_c(PCZ, i);
@@ -162,6 +219,10 @@ __device__ __forceinline__ void link_one(const CollideArgs& a, int i, uint16_t o
   int p = -1;
   if (o == OWN_WALL) {
     const bool lo = int(z) + cz == 0;
+    if (a.wall_type[lo ? 0 : 1] != 0) {
+      open_face<real, NC>(a, lo ? 0 : 1, i, j, s, x, y, z, fs, rho, u);
+      return;
+    }
     uwx = lo ? a.wall_lo[0] : a.wall_hi[0];
     uwy = lo ? a.wall_lo[1] : a.wall_hi[1];
     uwz = lo ? a.wall_lo[2] : a.wall_hi[2];
@@ -228,6 +289,7 @@ struct LinkQueue {
   real fs[NC][kDenseLinks<real> ? Q * 64 : QW];
   uint32_t x[64], y[64], z[64];
   real rho[NC][64];
+  real u[3][64];
 };
 
 // ---------------------------------------------------------------------------
@@ -447,6 +509,9 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
   lq.z[lane] = z;
 #pragma unroll
   for (int k = 0; k < NC; ++k) lq.rho[k][lane] = rho[k];
+  lq.u[0][lane] = ux;
+  lq.u[1][lane] = uy;
+  lq.u[2][lane] = uz;
   // the wave's own LDS writes, in order, before any lane reads them
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -461,7 +526,8 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
       fs[k] = lq.fs[k][kDenseLinks<real> ? i * 64 + src : e];
       rk[k] = lq.rho[k][src];
     }
-    link_one<real, NC>(a, i, o, lq.x[src], lq.y[src], lq.z[src], fs, rk, pid, lv);
+    const real us[3] = {lq.u[0][src], lq.u[1][src], lq.u[2][src]};
+    link_one<real, NC>(a, i, o, lq.x[src], lq.y[src], lq.z[src], fs, rk, us, pid, lv);
   }
   if (!queued) {
     // past the wave's capacity: this lane walks its own links, reading back
@@ -474,7 +540,8 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
       for (int k = 0; k < NC; ++k) fs[k] = ld32(fout + (size_t(k) * Q + i) * N, n);
       const uint32_t sn = nbr_dyn(x, y, z, dir_c(PCX, i), dir_c(PCY, i), dir_c(PCZ, i), a.nx,
                                   a.ny, a.nz);
-      link_one<real, NC>(a, i, ld32(a.owner, sn), x, y, z, fs, rho, pid, lv);
+      const real un[3] = {ux, uy, uz};
+      link_one<real, NC>(a, i, ld32(a.owner, sn), x, y, z, fs, rho, un, pid, lv);
     }
   }
   if (a.acc) flush_links(a.acc, pid, lv);
@@ -774,6 +841,11 @@ hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t
     a.wall_lo[d] = P.wall_u_lo[d];
     a.wall_hi[d] = P.wall_u_hi[d];
   }
+  for (int f = 0; f < 2; ++f) {
+    a.wall_type[f] = P.walls ? P.wall_type[f] : 0;
+    for (int k = 0; k < 2; ++k) a.wall_rho[f][k] = P.wall_rho[f][k];
+  }
+  a.ubnd = reinterpret_cast<const double*>(wptr(c, c->wl.ubnd));
   a.L[0] = g.nx;
   a.L[1] = g.ny;
   a.L[2] = g.nz;
@@ -795,6 +867,58 @@ hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t
     if (g.ncomp == 2) collide_t<float, 2>(c, a);
     else collide_t<float, 1>(c, a);
   }
+  return hipGetLastError();
+}
+
+bool has_pressure_face(const lb_params& p) {
+  return p.walls && (p.wall_type[0] == 1 || p.wall_type[1] == 1);
+}
+
+// Mixture velocity (Eq. scvel) of the nodes one layer inside each face layer,
+// z = 2 and z = nz - 3, from the populations of the step (node events done).
+template <typename real>
+__global__ void __launch_bounds__(BLOCK)
+k_face_velocity(const real* __restrict__ f, uint32_t nx, uint32_t ny, uint32_t nz, int ncomp,
+                double r0a, double r0b, double it0, double it1, double* __restrict__ ubnd) {
+  const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t plane = nx * ny;
+  if (t >= 2 * plane) return;
+  const int face = t < plane ? 0 : 1;
+  const uint32_t xy = t - face * plane, x = xy % nx, y = xy / nx;
+  const uint32_t z = face == 0 ? 2 : nz - 3;
+  const uint32_t N = plane * nz;
+  Nbr nb(x, y, z, nx, ny, nz);
+  double num[3] = {0, 0, 0}, den = 0;
+  for (int k = 0; k < ncomp; ++k) {
+    double s = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+      const double v = double(f[(size_t(k) * Q + i) * N + nb.pull(i)]);
+      s += v;
+      j[0] += v * CX[i];
+      j[1] += v * CY[i];
+      j[2] += v * CZ[i];
+    }
+    const double it = k == 0 ? it0 : it1;
+    for (int d = 0; d < 3; ++d) num[d] += j[d] * it;
+    den += ((k == 0 ? r0a : r0b) + s) * it;
+  }
+  for (int d = 0; d < 3; ++d) ubnd[size_t(t) * 3 + d] = num[d] / den;
+}
+
+hipError_t launch_face_velocity(lb_ctx* c, const void* f) {
+  const auto& g = c->geo;
+  const auto& P = c->P;
+  const int kb = g.ncomp == 2 ? 1 : 0;
+  double* ub = reinterpret_cast<double*>(wptr(c, c->wl.ubnd));
+  const dim3 grid(nblocks(2ull * g.nx * g.ny));
+  if (fp64(c))
+    hipLaunchKernelGGL(k_face_velocity<double>, grid, dim3(BLOCK), 0, c->stream,
+                       static_cast<const double*>(f), g.nx, g.ny, g.nz, g.ncomp, P.rho0[0],
+                       P.rho0[kb], 1.0 / P.tau[0], 1.0 / P.tau[kb], ub);
+  else
+    hipLaunchKernelGGL(k_face_velocity<float>, grid, dim3(BLOCK), 0, c->stream,
+                       static_cast<const float*>(f), g.nx, g.ny, g.nz, g.ncomp, P.rho0[0],
+                       P.rho0[kb], 1.0 / P.tau[0], 1.0 / P.tau[kb], ub);
   return hipGetLastError();
 }
 

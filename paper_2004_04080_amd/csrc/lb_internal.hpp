@@ -21,6 +21,7 @@ struct WorkLayout {
   size_t cell_ids = 0;     // int32[P]
   size_t staging = 0;      // double[staging_n]
   size_t staging_n = 0;
+  size_t ubnd = 0;         // double[2][nx*ny][3]: mixture velocity next to open faces
   size_t total = 0;
 };
 
@@ -97,6 +98,9 @@ hipError_t launch_density(lb_ctx* c, const void* f);
 hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t* owner,
                           bool forces = true);
 hipError_t launch_fill_walls(lb_ctx* c, const uint16_t* owner);
+// mixture velocity of the second fluid layer inside each pressure face
+hipError_t launch_face_velocity(lb_ctx* c, const void* f);
+bool has_pressure_face(const lb_params& p);
 hipError_t launch_get_populations(lb_ctx* c, int k, int i, uint32_t first, uint32_t count,
                                   double* out);
 hipError_t launch_set_populations(lb_ctx* c, int k, int i, uint32_t first, uint32_t count,

@@ -298,7 +298,7 @@ constexpr uint32_t kNeg2[3] = {dir_set(0, -1, 2), dir_set(1, -1, 2), dir_set(2, 
 // F = -G s sum_k psi_k(n) sum_{i: n+c_i fluid} w_i psi_kbar(n+c_i) c_i and the
 // torque about the sphere centre are summed into F_SC, T_SC of its sphere.
 // Wall nodes are left to the wall fill.
-template <typename real, int NC>
+template <typename real, int NC, bool JANUS>
 __global__ void __launch_bounds__(PBLOCK) k_fill_nodes(PArgs a) {
   const uint32_t n = blockIdx.x * PBLOCK + threadIdx.x;
   int pid = -1;
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(PBLOCK) k_fill_nodes(PArgs a) {
       double zeta[NC];
 #pragma unroll
       for (int k = 0; k < NC; ++k) zeta[k] = a.zeta[k];
-      if (a.janus) {
+      if (JANUS) {
         // Janus wetting: angle from the sphere's body x axis, smooth switch
         const double* P = a.ps + size_t(o - 1) * PSTRIDE;
         const double q0 = P[PS_Q], q1 = P[PS_Q + 1], q2 = P[PS_Q + 2], q3 = P[PS_Q + 3];
@@ -753,13 +753,18 @@ hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces) 
   PArgs a = pargs(c, const_cast<uint16_t*>(owner), owner);
   if (!forces) a.acc = nullptr;  // psi only: leave the force terms alone
   const dim3 grid((c->geo.N + PBLOCK - 1) / PBLOCK);
-  const bool two = c->geo.ncomp == 2;
+  const bool two = c->geo.ncomp == 2, janus = c->P.janus != 0;
+  const hipStream_t s = c->stream;
   if (c->geo.prec == LB_FP64) {
-    if (two) hipLaunchKernelGGL((k_fill_nodes<double, 2>), grid, dim3(PBLOCK), 0, c->stream, a);
-    else hipLaunchKernelGGL((k_fill_nodes<double, 1>), grid, dim3(PBLOCK), 0, c->stream, a);
+    if (two && janus) hipLaunchKernelGGL((k_fill_nodes<double, 2, true>), grid, dim3(PBLOCK), 0, s, a);
+    else if (two) hipLaunchKernelGGL((k_fill_nodes<double, 2, false>), grid, dim3(PBLOCK), 0, s, a);
+    else if (janus) hipLaunchKernelGGL((k_fill_nodes<double, 1, true>), grid, dim3(PBLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_fill_nodes<double, 1, false>), grid, dim3(PBLOCK), 0, s, a);
   } else {
-    if (two) hipLaunchKernelGGL((k_fill_nodes<float, 2>), grid, dim3(PBLOCK), 0, c->stream, a);
-    else hipLaunchKernelGGL((k_fill_nodes<float, 1>), grid, dim3(PBLOCK), 0, c->stream, a);
+    if (two && janus) hipLaunchKernelGGL((k_fill_nodes<float, 2, true>), grid, dim3(PBLOCK), 0, s, a);
+    else if (two) hipLaunchKernelGGL((k_fill_nodes<float, 2, false>), grid, dim3(PBLOCK), 0, s, a);
+    else if (janus) hipLaunchKernelGGL((k_fill_nodes<float, 1, true>), grid, dim3(PBLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_fill_nodes<float, 1, false>), grid, dim3(PBLOCK), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -50,6 +50,8 @@ class Params:
     lub_mu: float = 0.0
     lub_hn: float = 0.67
     lub_hcap: float = 0.5
+    wall_type: Sequence[int] = (0, 0)
+    wall_rho: Sequence[Sequence[float]] = ((1.0, 1.0), (1.0, 1.0))
 
     @property
     def N(self) -> int:
@@ -89,6 +91,8 @@ class Params:
         p.lub_mu = self.lub_mu
         p.lub_hn = self.lub_hn
         p.lub_hcap = self.lub_hcap
+        p.wall_type[:] = [int(v) for v in self.wall_type]
+        p.wall_rho[:] = [float(v) for face in self.wall_rho for v in face]
         return p
 
 

@@ -29,7 +29,7 @@ requires_gpu = pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
 _COMMON = ("ncomp", "tau", "G", "sc_norm", "g", "walls", "wall_u_lo", "wall_u_hi", "radius",
            "particle_density", "hertz_K", "hertz_d0", "hertz_rcap", "zeta", "rho_fallback",
            "rotate", "particles_fixed", "janus", "janus_theta0", "janus_width", "janus_zeta",
-           "lub_mu", "lub_hn", "lub_hcap")
+           "lub_mu", "lub_hn", "lub_hcap", "wall_type", "wall_rho")
 
 
 def make_pair(shape, rho, u0=None, x=None, v=None, w=None, precision="fp64", **kw):
