@@ -40,8 +40,8 @@ MUTATIONS = {
     "fluid_force_component": ("T r = rt[int64_t(kb) * N + nb[n * Q + i]] * WT[i];",
                               "T r = rt[int64_t(k) * N + nb[n * Q + i]] * WT[i];"),
     "mixture_velocity_weights": ("num[a] += jj[a] / P.tau[k];", "num[a] += jj[a];"),
-    "wall_sides_swapped": ("const double* U = (cz(s) == 0) ? P.wall_u_lo : P.wall_u_hi;",
-                           "const double* U = (cz(s) == 0) ? P.wall_u_hi : P.wall_u_lo;"),
+    "wall_sides_swapped": ("const int face = cz(s) == 0 ? 0 : 1;",
+                           "const int face = cz(s) == 0 ? 1 : 0;"),
     "equilibrium_quadrupole": ("return rho * WT[i] * (1.0 + dip + quad * 0.5);",
                                "return rho * WT[i] * (1.0 + dip + quad);"),
     "created_node_neighbours": (
