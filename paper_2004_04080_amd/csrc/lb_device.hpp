@@ -127,4 +127,40 @@ __device__ __forceinline__ int wrap_int(int v, int L) {
   return v < 0 ? v + L : v;
 }
 
+// Per-sphere sums of per-lane contributions, added with FP64 atomics into
+// acc[pid * ASTRIDE + off + c], c < NV. Consecutive lanes that carry the same
+// sphere id form a run (a wave covers consecutive nodes of one row, so the
+// nodes of one sphere in it are mostly adjacent). A segmented inclusive scan
+// over shifts 1, 2, 4, ..., which stops once no run is longer than the shift,
+// leaves each run's total in its last lane; that lane issues the atomics, one
+// per component. Lanes with pid < 0 contribute nothing. Every lane of the wave
+// calls this.
+template <int NV>
+__device__ __forceinline__ void flush_runs(double* __restrict__ acc, int off, int pid,
+                                           const double v[NV]) {
+  const int lane = __lane_id();
+  const int prev = __shfl_up(pid, 1);
+  const uint64_t heads = __ballot(lane == 0 || prev != pid);
+  if (!__ballot(pid >= 0)) return;
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int pos = lane - (63 - __clzll(heads & upto));  // position in the run
+  double s[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) s[c] = v[c];
+  for (int k = 1; k < 64; k <<= 1) {
+    if (!__ballot(pid >= 0 && pos >= k)) break;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      const double t = __shfl_up(s[c], k);
+      if (pos >= k) s[c] += t;
+    }
+  }
+  const bool last = lane == 63 || (((heads >> lane) >> 1) & 1ull);
+  if (pid >= 0 && last) {
+    double* A = acc + size_t(pid) * ASTRIDE + off;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) unsafeAtomicAdd(A + c, s[c]);
+  }
+}
+
 }  // namespace lbh

@@ -16,6 +16,8 @@ namespace lbh {
 constexpr int BLOCK = 256;
 
 static inline uint32_t nblocks(uint64_t n) { return uint32_t((n + BLOCK - 1) / BLOCK); }
+// target band width of the collide sweep, in workgroups per z-plane
+constexpr uint32_t kBandTarget = 64;
 
 // ---------------------------------------------------------------------------
 // Initial populations f_i = f_eq(rho0(n), u0(n)) (Eq. LEQ), written in pull form.
@@ -54,12 +56,15 @@ k_init(real* __restrict__ f, const double* __restrict__ rho0, const double* __re
 // ---------------------------------------------------------------------------
 // Moments of the pull-gathered populations: psi_k(n) - rho0_k = sum_i df_i.
 // Written for every node; solid nodes get overwritten by the fill kernels.
+// Each XCD sweeps one contiguous range of nodes, so that the lines a gather
+// shifted by one node shares with the neighbouring workgroup stay in its L2.
 // ---------------------------------------------------------------------------
 template <typename real, int NC>
 __global__ void __launch_bounds__(BLOCK)
 k_density(const real* __restrict__ f, real* __restrict__ psi, uint32_t nx, uint32_t ny,
-          uint32_t nz) {
-  const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+          uint32_t nz, uint32_t blocks_per_xcd) {
+  const uint32_t b = (blockIdx.x % 8u) * blocks_per_xcd + blockIdx.x / 8u;
+  const uint32_t n = b * BLOCK + threadIdx.x;
   const uint32_t N = nx * ny * nz;
   if (n >= N) return;
   uint32_t x, y, z;
@@ -70,8 +75,8 @@ k_density(const real* __restrict__ f, real* __restrict__ psi, uint32_t nx, uint3
     const real* fk = f + size_t(k) * Q * N;
     real s = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) s += fk[size_t(i) * N + nb.pull(i)];
-    psi[size_t(k) * N + n] = s;
+    for (int i = 0; i < Q; ++i) s += ld32(fk + size_t(i) * N, nb.pull(i));
+    st32(psi + size_t(k) * N, n, s);
   }
 }
 
@@ -96,6 +101,9 @@ struct CollideArgs {
   const double* ubnd;       // [2][nx*ny][3] mixture velocity one layer inside each face
   double L[3], invL[3];
   uint32_t blocks_per_xcd;  // workgroups per XCD (grid = 8 x blocks_per_xcd)
+  uint32_t nblk;            // workgroups that hold nodes
+  uint32_t band_w;          // workgroups per band and z-plane (0: whole planes)
+  uint32_t plane_w;         // workgroups per z-plane
 };
 
 // Packed direction tables for a direction index that varies per lane:
@@ -109,34 +117,6 @@ constexpr uint64_t PCX = pack_dir(CX), PCY = pack_dir(CY), PCZ = pack_dir(CZ);
 __device__ __forceinline__ int dir_c(uint64_t packed, int i) { return int((packed >> (2 * i)) & 3) - 1; }
 // opposite direction in the library's order (1<->2, 3<->4, 5<->6, 7<->8, 9..13<->14..18)
 __device__ __forceinline__ int dir_opp(int i) { return i <= 8 ? ((i - 1) ^ 1) + 1 : (i <= 13 ? i + 5 : i - 5); }
-
-// Wave-level segmented reduction of per-lane link force/torque contributions
-// keyed by sphere id, then one FP64 atomic per (wave, sphere, component).
-// Every lane of the wave must call this (lanes without contributions pass pid < 0).
-__device__ __forceinline__ void flush_links(double* __restrict__ acc, int pid, double v[7]) {
-  const int lane = __lane_id();
-  uint64_t pending = __ballot(pid >= 0);
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int lp = __shfl(pid, leader);
-    const bool mine = pid == lp;
-    double s[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) s[c] = mine ? v[c] : 0.0;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int c = 0; c < 7; ++c) s[c] += __shfl_xor(s[c], off);
-    if (lane == leader) {
-      double* a = acc + size_t(lp) * ASTRIDE;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) unsafeAtomicAdd(a + AC_FLIQ + c, s[c]);
-      unsafeAtomicAdd(a + AC_FLABS, s[6]);
-    }
-    if (mine) pid = -1;
-    pending = __ballot(pid >= 0);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Bounce-back of one link and its momentum exchange. Fluid node (x, y, z),
@@ -311,12 +291,26 @@ struct LinkQueue {
 // any branch on the map. A solid node writes zeros into the slots that no
 // link fills, so together with the reflections every slot of the output is
 // written. Workgroups are dealt round-robin over the 8 XCDs; the block index
-// is remapped so that each XCD sweeps one contiguous range of nodes and
-// neighbouring rows share that XCD's L2.
+// is remapped so that each XCD sweeps its own y-bands of the box, each band
+// through every z-plane (band_block), and neighbouring rows share that XCD's
+// L2.
 // ---------------------------------------------------------------------------
+// Order in which an XCD sweeps its workgroups. The box is cut along y into
+// bands of band_w workgroups per z-plane; the sweep takes one band through
+// every z-plane before the next band. The rows at z - 1 and z + 1 of a row
+// (its pseudo-potential neighbours, and the solid slots that its reflections
+// fill) are then handled within a few hundred workgroups of it, while they
+// still sit in the XCD's L2. Logical index s -> workgroup of nodes.
+__device__ __forceinline__ uint32_t band_block(const CollideArgs& a, uint32_t s) {
+  if (a.band_w == 0 || s >= a.nblk) return s;
+  const uint32_t w = s % a.band_w, t = s / a.band_w;
+  const uint32_t z = t % a.nz, band = t / a.nz;
+  return z * a.plane_w + band * a.band_w + w;
+}
+
 template <typename real, int NC, bool SOLIDS>
 __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
-  const uint32_t b = (blockIdx.x % 8u) * a.blocks_per_xcd + blockIdx.x / 8u;
+  const uint32_t b = band_block(a, (blockIdx.x % 8u) * a.blocks_per_xcd + blockIdx.x / 8u);
   const uint32_t n0 = b * BLOCK + threadIdx.x;
   const bool valid = n0 < a.N;
   const uint32_t N = a.N;
@@ -544,7 +538,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
       link_one<real, NC>(a, i, ld32(a.owner, sn), x, y, z, fs, rho, un, pid, lv);
     }
   }
-  if (a.acc) flush_links(a.acc, pid, lv);
+  if (a.acc) flush_runs<7>(a.acc, AC_FLIQ, pid, lv);
 }
 
 // ---------------------------------------------------------------------------
@@ -790,24 +784,23 @@ hipError_t launch_init_populations(lb_ctx* c, const double* rho0, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_density(lb_ctx* c, const void* f) {
+template <typename real>
+static void density_t(lb_ctx* c, const void* f) {
   const auto& g = c->geo;
-  dim3 grid(nblocks(g.N));
-  if (fp64(c)) {
-    if (g.ncomp == 2)
-      hipLaunchKernelGGL((k_density<double, 2>), grid, dim3(BLOCK), 0, c->stream,
-                         static_cast<const double*>(f), static_cast<double*>(c->B.rho), g.nx, g.ny, g.nz);
-    else
-      hipLaunchKernelGGL((k_density<double, 1>), grid, dim3(BLOCK), 0, c->stream,
-                         static_cast<const double*>(f), static_cast<double*>(c->B.rho), g.nx, g.ny, g.nz);
-  } else {
-    if (g.ncomp == 2)
-      hipLaunchKernelGGL((k_density<float, 2>), grid, dim3(BLOCK), 0, c->stream,
-                         static_cast<const float*>(f), static_cast<float*>(c->B.rho), g.nx, g.ny, g.nz);
-    else
-      hipLaunchKernelGGL((k_density<float, 1>), grid, dim3(BLOCK), 0, c->stream,
-                         static_cast<const float*>(f), static_cast<float*>(c->B.rho), g.nx, g.ny, g.nz);
-  }
+  const uint32_t bpx = (nblocks(g.N) + 7) / 8;
+  const real* fr = static_cast<const real*>(f);
+  real* psi = static_cast<real*>(c->B.rho);
+  if (g.ncomp == 2)
+    hipLaunchKernelGGL((k_density<real, 2>), dim3(8u * bpx), dim3(BLOCK), 0, c->stream, fr, psi,
+                       g.nx, g.ny, g.nz, bpx);
+  else
+    hipLaunchKernelGGL((k_density<real, 1>), dim3(8u * bpx), dim3(BLOCK), 0, c->stream, fr, psi,
+                       g.nx, g.ny, g.nz, bpx);
+}
+
+hipError_t launch_density(lb_ctx* c, const void* f) {
+  if (fp64(c)) density_t<double>(c, f);
+  else density_t<float>(c, f);
   return hipGetLastError();
 }
 
@@ -850,7 +843,20 @@ hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t
   a.L[1] = g.ny;
   a.L[2] = g.nz;
   for (int d = 0; d < 3; ++d) a.invL[d] = 1.0 / a.L[d];
-  a.blocks_per_xcd = (nblocks(g.N) + 7) / 8;
+  a.nblk = nblocks(g.N);
+  a.blocks_per_xcd = (a.nblk + 7) / 8;
+  // bands of about 32 workgroups (8192 nodes) per z-plane, when whole
+  // workgroups tile a z-plane; otherwise plain plane order
+  a.band_w = 0;
+  a.plane_w = 0;
+  if ((uint64_t(g.nx) * g.ny) % BLOCK == 0) {
+    a.plane_w = uint32_t(uint64_t(g.nx) * g.ny / BLOCK);
+    for (uint32_t w = std::min(kBandTarget, a.plane_w); w >= 1; --w)
+      if (a.plane_w % w == 0) {
+        a.band_w = w;
+        break;
+      }
+  }
   const int kb = g.ncomp == 2 ? 1 : 0;
   a.rho0[0] = P.rho0[0];
   a.rho0[1] = P.rho0[kb];

@@ -157,35 +157,6 @@ __global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which) {
   }
 }
 
-// Wave-level segmented sum of per-lane contributions keyed by sphere id, then
-// one FP64 atomic per (wave, sphere, component) into acc[p][off + 0..NV-1].
-// Every lane of the wave calls it (lanes without a contribution pass pid < 0).
-template <int NV>
-__device__ __forceinline__ void flush_sphere_sums(double* __restrict__ acc, int off, int pid,
-                                                  const double v[NV]) {
-  const int lane = __lane_id();
-  uint64_t pending = __ballot(pid >= 0);
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int lp = __shfl(pid, leader);
-    const bool mine = pid == lp;
-    double s[NV];
-#pragma unroll
-    for (int c = 0; c < NV; ++c) s[c] = mine ? v[c] : 0.0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-      for (int c = 0; c < NV; ++c) s[c] += __shfl_xor(s[c], o);
-    if (lane == leader) {
-      double* A = acc + size_t(lp) * ASTRIDE + off;
-#pragma unroll
-      for (int c = 0; c < NV; ++c) unsafeAtomicAdd(A + c, s[c]);
-    }
-    if (mine) pid = -1;
-    pending = __ballot(pid >= 0);
-  }
-}
-
 // Fluid-node destruction (Eq. distr) and creation (Eq. creat), one thread per
 // node, from the map of the current populations (own_old) and the new map
 // (own_new). A destroyed node hands its bare momentum sum_k j_k to its new
@@ -271,7 +242,7 @@ __global__ void __launch_bounds__(PBLOCK) k_events(PArgs a) {
       v[11] = -(d[0] * M[1] - d[1] * M[0]);
     }
   }
-  flush_sphere_sums<12>(a.acc, AC_FD, pid, v);
+  flush_runs<12>(a.acc, AC_FD, pid, v);
 }
 
 // Direction sets as bit masks over the 18 moving directions: axis and
@@ -397,7 +368,7 @@ __global__ void __launch_bounds__(PBLOCK) k_fill_nodes(PArgs a) {
       }
     }
   }
-  if (NC == 2 && a.acc) flush_sphere_sums<6>(a.acc, AC_FSC, pid, v);
+  if (NC == 2 && a.acc) flush_runs<6>(a.acc, AC_FSC, pid, v);
 }
 
 // ---------------------------------------------------------------------------
