@@ -145,7 +145,8 @@ typedef struct lb_obs {
   double  particle_ke;   /* sum 1/2 m v^2                                              */
   double  particle_ke_rot; /* sum 1/2 I w^2                                            */
   int32_t nparticles;
-  int32_t flags;         /* bit 0: particle speed exceeded, bit 1: non-finite fluid    */
+  int32_t flags;         /* bit 0: particle speed exceeded, bit 1: non-finite fluid,
+                            bit 2: frontier list overflow (ruled out by its sizing)    */
 } lb_obs;
 
 /* Per-sphere record of lb_get_particles / lb_set_particles, FP64, in this order. */

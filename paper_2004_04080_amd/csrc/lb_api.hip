@@ -235,6 +235,17 @@ size_t work_layout(const lb_params& p, WorkLayout& wl, int ncell_total) {
   off = align_up(off + wl.staging_n * sizeof(double));
   wl.ubnd = off;
   if (has_pressure_face(p)) off = align_up(off + 2 * size_t(p.nx) * p.ny * 3 * sizeof(double));
+  // Frontier list: a sphere owns only nodes closer than R to its centre, and
+  // the unit cubes around those nodes lie inside the ball of radius R + 1, so
+  // a sphere owns fewer than 4/3 pi (R + 1)^3 nodes.
+  wl.fcount = off;
+  off = align_up(off + sizeof(int32_t));
+  const double rr = std::max(p.radius, 0.0) + 1.0;
+  const size_t per = size_t(std::ceil(4.0 / 3.0 * M_PI * rr * rr * rr));
+  wl.fcap = std::min(N, size_t(std::max(p.max_particles, 0)) * per);
+  wl.fcap = std::min<size_t>(wl.fcap, 0xFFFFFFFFu);
+  wl.flist = off;
+  off = align_up(off + wl.fcap * 2 * sizeof(uint32_t));
   wl.total = off;
   return off;
 }
@@ -505,7 +516,7 @@ int lb_step(lb_ctx* c, int32_t nsteps) {
     if (has_pressure_face(c->P)) HIPCHK(c, launch_face_velocity(c, fin));
     if (c->nparticles > 0 || c->P.walls) {
       Phase ph(c, 2);
-      if (c->nparticles > 0) HIPCHK(c, launch_fill_particles(c, own, true));
+      if (c->nparticles > 0) HIPCHK(c, launch_fill_particles(c, own, true, moving));
       if (c->P.walls) HIPCHK(c, launch_fill_walls(c, own));
     }
     {
@@ -627,7 +638,7 @@ int lb_observables(lb_ctx* c, lb_obs* o) {
   double* red = reinterpret_cast<double*>(wptr(c, c->wl.red_out));
   HIPCHK(c, launch_reduce(c, red));
   double r[RED_N];
-  int32_t flags[2];
+  int32_t flags[3];
   HIPCHK(c, hipMemcpyAsync(r, red, sizeof(r), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(flags, wptr(c, c->wl.flags), sizeof(flags), hipMemcpyDeviceToHost,
                            c->stream));
@@ -666,9 +677,10 @@ int lb_observables(lb_ctx* c, lb_obs* o) {
   o->particle_ke_rot = nsum([&](const double* P) {
     return 0.5 * c->inertia * (P[PS_W] * P[PS_W] + P[PS_W + 1] * P[PS_W + 1] + P[PS_W + 2] * P[PS_W + 2]);
   });
-  o->flags = (flags[0] ? 1 : 0) | (r[11] > 0 || !std::isfinite(r[0]) ? 2 : 0);
+  o->flags = (flags[0] ? 1 : 0) | (r[11] > 0 || !std::isfinite(r[0]) ? 2 : 0) | (flags[2] ? 4 : 0);
   if (o->flags & 1) return fail(c, LB_E_PARTICLE_SPEED, "sphere speed exceeded 1/2 per step");
   if (o->flags & 2) return fail(c, LB_E_NONFINITE, "non-finite populations");
+  if (o->flags & 4) return fail(c, LB_E_CAPACITY, "frontier list overflow");
   return LB_OK;
 }
 

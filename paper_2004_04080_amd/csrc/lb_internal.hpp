@@ -22,6 +22,9 @@ struct WorkLayout {
   size_t staging = 0;      // double[staging_n]
   size_t staging_n = 0;
   size_t ubnd = 0;         // double[2][nx*ny][3]: mixture velocity next to open faces
+  size_t fcount = 0;       // int32: entries appended to the frontier list
+  size_t flist = 0;        // uint2[fcap]: frontier nodes of the sphere map (node, mask)
+  size_t fcap = 0;
   size_t total = 0;
 };
 
@@ -115,7 +118,14 @@ hipError_t launch_owner_to_int(lb_ctx* c, const uint16_t* owner, uint32_t first,
 hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner);   // walls + all spheres at x
 hipError_t launch_map_update(lb_ctx* c, hipStream_t s);  // clear, unraster, raster, pairs
 hipError_t launch_events(lb_ctx* c);                     // node creation / destruction
-hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces);
+// frontier list of the sphere map `owner`, whose spheres sit around the
+// centres at record offset `which`, on stream s
+hipError_t launch_frontier(lb_ctx* c, const uint16_t* owner, int which, hipStream_t s);
+// virtual densities (and with forces on, F_SC and T_SC) of the frontier of
+// `owner`; builds the list of the current map first unless list_ready (the
+// list of the new map, built by launch_map_update)
+hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces,
+                                 bool list_ready = false);
 hipError_t launch_integrate(lb_ctx* c);
 hipError_t launch_clear_accumulators(lb_ctx* c);
 

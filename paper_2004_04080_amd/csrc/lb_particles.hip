@@ -41,11 +41,20 @@ __device__ __forceinline__ Box sphere_box(const double c[3], double R) {
   return b;
 }
 
-__device__ __forceinline__ void box_node(const Box& b, int t, int& x, int& y, int& z) {
-  x = b.lo[0] + t % b.n[0];
-  const int r = t / b.n[0];
-  y = b.lo[1] + r % b.n[1];
-  z = b.lo[2] + r / b.n[1];
+// Visit every node (x, y, z) of box b with the workgroup laid out as 16 x 16
+// threads over (x, y), every thread walking all z: no divisions in the walk.
+template <typename F>
+__device__ __forceinline__ void for_box(const Box& b, F&& f) {
+  static_assert(PBLOCK == 256, "16 x 16 thread layout");
+  const int tx = int(threadIdx.x & 15u), ty = int(threadIdx.x >> 4);
+  for (int k = 0; k < b.n[2]; ++k)
+    for (int j = ty; j < b.n[1]; j += 16)
+      for (int i = tx; i < b.n[0]; i += 16) f(b.lo[0] + i, b.lo[1] + j, b.lo[2] + k);
+}
+
+// periodic image in [0, L); box coordinates stray from [0, L) by at most R + 1
+__device__ __forceinline__ int wrap_box(int v, int L) {
+  return unsigned(v) < unsigned(L) ? v : (v < 0 && v >= -L ? v + L : (v >= L && v < 2 * L ? v - L : wrap_int(v, L)));
 }
 
 struct PArgs {
@@ -69,6 +78,14 @@ struct PArgs {
   int np;
   int janus;
   double janus_theta0, janus_width, janus_zeta[2];
+};
+
+// Frontier nodes of the sphere map: entries (node, fluid-neighbour mask),
+// count appended so far (cleared before each build), capacity.
+struct FrontierList {
+  uint2* list;
+  int32_t* count;
+  uint32_t cap;
 };
 
 // Sum NV doubles over the workgroup; thread 0 gets the result.
@@ -110,12 +127,11 @@ __global__ void __launch_bounds__(PBLOCK) k_unraster(PArgs a, int which) {
   const double c[3] = {P[which], P[which + 1], P[which + 2]};
   const Box b = sphere_box(c, a.R);
   const uint16_t me = uint16_t(p + 1);
-  for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
-    int x, y, z;
-    box_node(b, t, x, y, z);
-    const uint32_t n = wrap_int(x, a.nx) + a.nx * (wrap_int(y, a.ny) + a.ny * wrap_int(z, a.nz));
+  for_box(b, [&](int x, int y, int z) {
+    const uint32_t n = uint32_t(wrap_box(x, a.nx)) +
+                       uint32_t(a.nx) * (uint32_t(wrap_box(y, a.ny)) + uint32_t(a.ny) * uint32_t(wrap_box(z, a.nz)));
     if (a.own_new[n] == me) a.own_new[n] = 0;
-  }
+  });
 }
 
 // Lowest sphere index wins a node claimed by several spheres; walls stay walls.
@@ -144,17 +160,15 @@ __global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which) {
     const double vmax = fmax(fabs(P[PS_V]), fmax(fabs(P[PS_V + 1]), fabs(P[PS_V + 2])));
     if (!(vmax <= 0.5)) atomicOr(a.flags, 1);
   }
-  for (int t = threadIdx.x; t < b.total; t += PBLOCK) {
-    int x, y, z;
-    box_node(b, t, x, y, z);
-    const int wx = wrap_int(x, a.nx), wy = wrap_int(y, a.ny), wz = wrap_int(z, a.nz);
-    if (a.walls && (wz == 0 || wz == a.nz - 1)) continue;
+  for_box(b, [&](int x, int y, int z) {
+    const int wx = wrap_box(x, a.nx), wy = wrap_box(y, a.ny), wz = wrap_box(z, a.nz);
+    if (a.walls && (wz == 0 || wz == a.nz - 1)) return;
     const double dx = min_image(wx - c[0], a.L[0]);
     const double dy = min_image(wy - c[1], a.L[1]);
     const double dz = min_image(wz - c[2], a.L[2]);
     if (dx * dx + dy * dy + dz * dz < R2)
       claim(a.own_new, uint32_t(wx) + a.nx * (uint32_t(wy) + a.ny * uint32_t(wz)), uint16_t(p + 1));
-  }
+  });
 }
 
 // Fluid-node destruction (Eq. distr) and creation (Eq. creat), one thread per
@@ -262,6 +276,73 @@ constexpr uint32_t kNeg1[3] = {dir_set(0, -1, 1), dir_set(1, -1, 1), dir_set(2, 
 constexpr uint32_t kPos2[3] = {dir_set(0, 1, 2), dir_set(1, 1, 2), dir_set(2, 1, 2)};
 constexpr uint32_t kNeg2[3] = {dir_set(0, -1, 2), dir_set(1, -1, 2), dir_set(2, -1, 2)};
 
+// Frontier list of a sphere map: every node of a sphere with at least one
+// fluid neighbour, as (node, mask of the directions i with n + c_i fluid).
+// The map holds sphere p around the centre at offset `which` of its record.
+// One workgroup per sphere walks its box and appends the nodes the sphere
+// owns, a wave at a time, so the entries of one sphere sit together. Along
+// an axis shorter than the box, one period of the box is walked, so that no
+// node is listed twice.
+__global__ void __launch_bounds__(PBLOCK) k_frontier(PArgs a, FrontierList fl, int which) {
+  // entries are staged in LDS and moved to the list in blocks, so that the
+  // shared counter takes one atomic per block of entries, not one per wave
+  constexpr int STAGE = 1024;
+  __shared__ uint2 stage[STAGE];
+  __shared__ int staged, base;
+  const int p = blockIdx.x;
+  const double* P = a.ps + size_t(p) * PSTRIDE;
+  const double c[3] = {P[which], P[which + 1], P[which + 2]};
+  const Box b = sphere_box(c, a.R);
+  const int nb0 = min(b.n[0], a.nx), nb1 = min(b.n[1], a.ny), nb2 = min(b.n[2], a.nz);
+  const uint16_t me = uint16_t(p + 1);
+  const int tx = int(threadIdx.x & 15u), ty = int(threadIdx.x >> 4);
+  const int lane = __lane_id();
+  if (threadIdx.x == 0) staged = 0;
+  auto flush = [&]() {
+    if (threadIdx.x == 0) base = atomicAdd(fl.count, staged);
+    __syncthreads();
+    for (int t = int(threadIdx.x); t < staged; t += PBLOCK)
+      if (uint32_t(base + t) < fl.cap) fl.list[base + t] = stage[t];
+    __syncthreads();
+    if (threadIdx.x == 0) staged = 0;
+  };
+  // trip counts are uniform over the workgroup: every thread reaches the barriers
+  for (int k = 0; k < nb2; ++k)
+    for (int jb = 0; jb < nb1; jb += 16)
+      for (int ib = 0; ib < nb0; ib += 16) {
+        const int i = ib + tx, j = jb + ty;
+        uint32_t n = 0, mask = 0;
+        if (i < nb0 && j < nb1) {
+          const uint32_t wx = uint32_t(wrap_box(b.lo[0] + i, a.nx));
+          const uint32_t wy = uint32_t(wrap_box(b.lo[1] + j, a.ny));
+          const uint32_t wz = uint32_t(wrap_box(b.lo[2] + k, a.nz));
+          n = wx + uint32_t(a.nx) * (wy + uint32_t(a.ny) * wz);
+          if (a.own_new[n] == me) {
+            Nbr nbr(wx, wy, wz, uint32_t(a.nx), uint32_t(a.ny), uint32_t(a.nz));
+#pragma unroll
+            for (int d = 1; d < Q; ++d)
+              if (a.own_new[nbr.push(d)] == 0) mask |= 1u << d;
+          }
+        }
+        __syncthreads();
+        const int cur = staged;  // the same value in every thread
+        __syncthreads();
+        if (cur > STAGE - PBLOCK) {  // room for one entry per thread
+          flush();
+          __syncthreads();
+        }
+        const uint64_t has = __ballot(mask != 0);
+        if (has) {
+          int w = 0;
+          if (lane == 0) w = atomicAdd(&staged, int(__popcll(has)));
+          w = __shfl(w, 0);
+          if (mask != 0) stage[w + int(__popcll(has & ((1ull << lane) - 1ull)))] = make_uint2(n, mask);
+        }
+      }
+  __syncthreads();
+  if (staged > 0) flush();
+}
+
 // Virtual densities on the sphere frontier (Eq. soliddens) and the Shan-Chen
 // force those nodes feel (Eq. shanchen2), one thread per node: a solid node
 // of a sphere with at least one fluid neighbour takes the w-weighted mean of
@@ -269,106 +350,122 @@ constexpr uint32_t kNeg2[3] = {dir_set(0, -1, 2), dir_set(1, -1, 2), dir_set(2, 
 // F = -G s sum_k psi_k(n) sum_{i: n+c_i fluid} w_i psi_kbar(n+c_i) c_i and the
 // torque about the sphere centre are summed into F_SC, T_SC of its sphere.
 // Wall nodes are left to the wall fill.
+//
+// The frontier nodes come from a list (k_frontier), one thread per entry, so
+// that the waves are full: walking every node of the box instead leaves most
+// lanes of a wave idle, since a wave crossing a sphere holds a handful of its
+// frontier nodes among fluid and interior nodes.
+// One frontier node n of sphere o with fluid-neighbour mask `mask`: its
+// virtual densities, and with forces on its Shan-Chen force and torque
+// (v, for sphere pid).
 template <typename real, int NC, bool JANUS>
-__global__ void __launch_bounds__(PBLOCK) k_fill_nodes(PArgs a) {
-  const uint32_t n = blockIdx.x * PBLOCK + threadIdx.x;
-  int pid = -1;
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  const uint16_t o = n < a.N ? a.own_new[n] : uint16_t(0);
-  if (o != 0 && o != OWN_WALL) {
-    uint32_t x, y, z;
-    node_xyz(n, uint32_t(a.nx), uint32_t(a.ny), x, y, z);
-    Nbr nb(x, y, z, uint32_t(a.nx), uint32_t(a.ny), uint32_t(a.nz));
-    uint32_t mask = 0;
+__device__ __forceinline__ void fill_one(const PArgs& a, uint32_t n, uint32_t mask, uint16_t o,
+                                         int& pid, double v[6]) {
+  uint32_t x, y, z;
+  node_xyz(n, uint32_t(a.nx), uint32_t(a.ny), x, y, z);
+  Nbr nb(x, y, z, uint32_t(a.nx), uint32_t(a.ny), uint32_t(a.nz));
+  real* psi = static_cast<real*>(a.psi);
+  const uint32_t N = a.N;
+  // weights over the fluid neighbours from the mask alone: sum w_i and
+  // sum w_i c_i, axis (1/18) and diagonal (1/36) directions counted apart
+  // (__popc is unsigned: counts are taken as int before differencing)
+  auto cnt = [&](uint32_t set) { return int(__popc(mask & set)); };
+  const double wsum = W1 * cnt(kAxisDirs) + W2 * cnt(kDiagDirs);
+  double Ws[3];
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-      if (a.own_new[nb.push(i)] == 0) mask |= 1u << i;
-    if (mask) {
-      real* psi = static_cast<real*>(a.psi);
-      const uint32_t N = a.N;
-      // weights over the fluid neighbours from the mask alone: sum w_i and
-      // sum w_i c_i, axis (1/18) and diagonal (1/36) directions counted apart
-      // (__popc is unsigned: counts are taken as int before differencing)
-      auto cnt = [&](uint32_t set) { return int(__popc(mask & set)); };
-      const double wsum = W1 * cnt(kAxisDirs) + W2 * cnt(kDiagDirs);
-      double Ws[3];
+  for (int d = 0; d < 3; ++d)
+    Ws[d] = W1 * (cnt(kPos1[d]) - cnt(kNeg1[d])) + W2 * (cnt(kPos2[d]) - cnt(kNeg2[d]));
+  // sum_i w_i psi_k(n + c_i) and sum_i w_i psi_k(n + c_i) c_i over the
+  // fluid neighbours, in the storage precision, by weight class
+  double sk[NC], gk[NC][3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        Ws[d] = W1 * (cnt(kPos1[d]) - cnt(kNeg1[d])) + W2 * (cnt(kPos2[d]) - cnt(kNeg2[d]));
-      // sum_i w_i psi_k(n + c_i) and sum_i w_i psi_k(n + c_i) c_i over the
-      // fluid neighbours, in the storage precision, by weight class
-      double sk[NC], gk[NC][3];
+  for (int k = 0; k < NC; ++k) {
+    const real* pk = psi + size_t(k) * N;
+    real s1 = 0, s2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const real* pk = psi + size_t(k) * N;
-        real s1 = 0, s2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
+    for (int i = 1; i < Q; ++i) {
+      const real pv = (mask & (1u << i)) ? pk[nb.push(i)] : real(0);
+      const int c[3] = {CX[i], CY[i], CZ[i]};
+      if (axis_dir(i)) s1 += pv;
+      else s2 += pv;
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          const real pv = (mask & (1u << i)) ? pk[nb.push(i)] : real(0);
-          const int c[3] = {CX[i], CY[i], CZ[i]};
-          if (axis_dir(i)) s1 += pv;
-          else s2 += pv;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            if (!c[d]) continue;
-            if (axis_dir(i)) g1[d] += c[d] > 0 ? pv : -pv;
-            else g2[d] += c[d] > 0 ? pv : -pv;
-          }
-        }
-        sk[k] = W1 * double(s1) + W2 * double(s2);
-        for (int d = 0; d < 3; ++d) gk[k][d] = W1 * double(g1[d]) + W2 * double(g2[d]);
-      }
-      double zeta[NC];
-#pragma unroll
-      for (int k = 0; k < NC; ++k) zeta[k] = a.zeta[k];
-      if (JANUS) {
-        // Janus wetting: angle from the sphere's body x axis, smooth switch
-        const double* P = a.ps + size_t(o - 1) * PSTRIDE;
-        const double q0 = P[PS_Q], q1 = P[PS_Q + 1], q2 = P[PS_Q + 2], q3 = P[PS_Q + 3];
-        const double ax[3] = {q0 * q0 + q1 * q1 - q2 * q2 - q3 * q3, 2 * (q1 * q2 + q0 * q3),
-                              2 * (q1 * q3 - q0 * q2)};
-        const double d[3] = {min_image(double(x) - P[PS_X], a.L[0]),
-                             min_image(double(y) - P[PS_X + 1], a.L[1]),
-                             min_image(double(z) - P[PS_X + 2], a.L[2])};
-        const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const double an = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-        double cth = (d[0] * ax[0] + d[1] * ax[1] + d[2] * ax[2]) / (dn * an);
-        cth = fmin(1.0, fmax(-1.0, cth));
-        const double theta = acos(cth) * (180.0 / M_PI);
-        double t = (a.janus_theta0 + 0.5 * a.janus_width - theta) / a.janus_width;
-        t = fmin(1.0, fmax(0.0, t));
-        const double S = 2.0 * t * t * (3.0 - 2.0 * t) - 1.0;
-        zeta[0] = a.janus_zeta[0] * S;
-        if (NC == 2) zeta[NC - 1] = -a.janus_zeta[1] * S;
-      }
-      double dv[NC];
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        dv[k] = zeta[k] * a.rho0[k] + (1.0 + zeta[k]) * sk[k] / wsum;
-        psi[size_t(k) * N + n] = real(dv[k]);
-      }
-      if (NC == 2 && a.acc) {
-        double F[3] = {0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-          const int kb = NC - 1 - k;
-          const double pk = a.rho0[k] + dv[k];
-          for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + gk[kb][c]);
-        }
-        pid = int(o) - 1;
-        const double* P = a.ps + size_t(pid) * PSTRIDE;
-        double d[3] = {double(x) - P[PS_X], double(y) - P[PS_X + 1], double(z) - P[PS_X + 2]};
-        for (int c = 0; c < 3; ++c) d[c] -= a.L[c] * rint(d[c] * a.invL[c]);
-        v[0] = F[0];
-        v[1] = F[1];
-        v[2] = F[2];
-        v[3] = d[1] * F[2] - d[2] * F[1];
-        v[4] = d[2] * F[0] - d[0] * F[2];
-        v[5] = d[0] * F[1] - d[1] * F[0];
+      for (int d = 0; d < 3; ++d) {
+        if (!c[d]) continue;
+        if (axis_dir(i)) g1[d] += c[d] > 0 ? pv : -pv;
+        else g2[d] += c[d] > 0 ? pv : -pv;
       }
     }
+    sk[k] = W1 * double(s1) + W2 * double(s2);
+    for (int d = 0; d < 3; ++d) gk[k][d] = W1 * double(g1[d]) + W2 * double(g2[d]);
   }
-  if (NC == 2 && a.acc) flush_runs<6>(a.acc, AC_FSC, pid, v);
+  double zeta[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) zeta[k] = a.zeta[k];
+  if (JANUS) {
+    // Janus wetting: angle from the sphere's body x axis, smooth switch
+    const double* P = a.ps + size_t(o - 1) * PSTRIDE;
+    const double q0 = P[PS_Q], q1 = P[PS_Q + 1], q2 = P[PS_Q + 2], q3 = P[PS_Q + 3];
+    const double ax[3] = {q0 * q0 + q1 * q1 - q2 * q2 - q3 * q3, 2 * (q1 * q2 + q0 * q3),
+                          2 * (q1 * q3 - q0 * q2)};
+    const double d[3] = {min_image(double(x) - P[PS_X], a.L[0]),
+                         min_image(double(y) - P[PS_X + 1], a.L[1]),
+                         min_image(double(z) - P[PS_X + 2], a.L[2])};
+    const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double an = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    double cth = (d[0] * ax[0] + d[1] * ax[1] + d[2] * ax[2]) / (dn * an);
+    cth = fmin(1.0, fmax(-1.0, cth));
+    const double theta = acos(cth) * (180.0 / M_PI);
+    double t = (a.janus_theta0 + 0.5 * a.janus_width - theta) / a.janus_width;
+    t = fmin(1.0, fmax(0.0, t));
+    const double S = 2.0 * t * t * (3.0 - 2.0 * t) - 1.0;
+    zeta[0] = a.janus_zeta[0] * S;
+    if (NC == 2) zeta[NC - 1] = -a.janus_zeta[1] * S;
+  }
+  double dv[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    dv[k] = zeta[k] * a.rho0[k] + (1.0 + zeta[k]) * sk[k] / wsum;
+    psi[size_t(k) * N + n] = real(dv[k]);
+  }
+  if (NC == 2 && a.acc) {
+    double F[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int kb = NC - 1 - k;
+      const double pk = a.rho0[k] + dv[k];
+      for (int c = 0; c < 3; ++c) F[c] -= a.Gs * pk * (a.rho0[kb] * Ws[c] + gk[kb][c]);
+    }
+    pid = int(o) - 1;
+    const double* P = a.ps + size_t(pid) * PSTRIDE;
+    double d[3] = {double(x) - P[PS_X], double(y) - P[PS_X + 1], double(z) - P[PS_X + 2]};
+    for (int c = 0; c < 3; ++c) d[c] -= a.L[c] * rint(d[c] * a.invL[c]);
+    v[0] = F[0];
+    v[1] = F[1];
+    v[2] = F[2];
+    v[3] = d[1] * F[2] - d[2] * F[1];
+    v[4] = d[2] * F[0] - d[0] * F[2];
+    v[5] = d[0] * F[1] - d[1] * F[0];
+  }
+}
+
+template <typename real, int NC, bool JANUS>
+__global__ void __launch_bounds__(PBLOCK) k_fill_list(PArgs a, FrontierList fl) {
+  const uint32_t total = min(uint32_t(*fl.count), fl.cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && uint32_t(*fl.count) > fl.cap && a.flags)
+    atomicOr(a.flags + 2, 1);  // list overflow (the capacity bound rules it out)
+  const uint32_t nwaves = gridDim.x * (PBLOCK / 64);
+  // whole waves step together through the list: flush_runs needs every lane
+  for (uint32_t base = (blockIdx.x * PBLOCK + threadIdx.x) / 64 * 64; base < total;
+       base += nwaves * 64) {
+    const uint32_t e = base + __lane_id();
+    int pid = -1;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (e < total) {
+      const uint2 en = fl.list[e];
+      fill_one<real, NC, JANUS>(a, en.x, en.y, a.own_new[en.x], pid, v);
+    }
+    if (NC == 2 && a.acc) flush_runs<6>(a.acc, AC_FSC, pid, v);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -666,6 +763,8 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   if (e0 != hipSuccess) return e0;
   hipLaunchKernelGGL(k_unraster, gp, bp, 0, s, a, int(PS_XRB));
   hipLaunchKernelGGL(k_raster, gp, bp, 0, s, a, int(PS_X));
+  e0 = launch_frontier(c, own_new, int(PS_X), s);
+  if (e0 != hipSuccess) return e0;
   // Hertz pairs through the cell list
   CellArgs ca;
   ca.ps = pstate(c);
@@ -720,22 +819,48 @@ hipError_t launch_events(lb_ctx* c) {
   return hipGetLastError();
 }
 
-hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces) {
+static FrontierList frontier_list(lb_ctx* c) {
+  FrontierList fl;
+  fl.list = reinterpret_cast<uint2*>(wptr(c, c->wl.flist));
+  fl.count = reinterpret_cast<int32_t*>(wptr(c, c->wl.fcount));
+  fl.cap = uint32_t(c->wl.fcap);
+  return fl;
+}
+
+hipError_t launch_frontier(lb_ctx* c, const uint16_t* owner, int which, hipStream_t s) {
+  const FrontierList fl = frontier_list(c);
+  const hipError_t e = hipMemsetAsync(fl.count, 0, sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  if (c->nparticles > 0)
+    hipLaunchKernelGGL(k_frontier, dim3(c->nparticles), dim3(PBLOCK), 0, s,
+                       pargs(c, const_cast<uint16_t*>(owner), owner), fl, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces, bool list_ready) {
+  if (!list_ready) {
+    // the current map: rasterised around the centres of the last step
+    const hipError_t e = launch_frontier(c, owner, int(PS_XRA), c->stream);
+    if (e != hipSuccess) return e;
+  }
   PArgs a = pargs(c, const_cast<uint16_t*>(owner), owner);
   if (!forces) a.acc = nullptr;  // psi only: leave the force terms alone
-  const dim3 grid((c->geo.N + PBLOCK - 1) / PBLOCK);
+  const FrontierList fl = frontier_list(c);
+  if (fl.cap == 0) return hipSuccess;
+  // enough waves to cover the list in a few passes
+  const dim3 grid(uint32_t(std::min<size_t>((c->wl.fcap + PBLOCK - 1) / PBLOCK, 8192)));
   const bool two = c->geo.ncomp == 2, janus = c->P.janus != 0;
   const hipStream_t s = c->stream;
   if (c->geo.prec == LB_FP64) {
-    if (two && janus) hipLaunchKernelGGL((k_fill_nodes<double, 2, true>), grid, dim3(PBLOCK), 0, s, a);
-    else if (two) hipLaunchKernelGGL((k_fill_nodes<double, 2, false>), grid, dim3(PBLOCK), 0, s, a);
-    else if (janus) hipLaunchKernelGGL((k_fill_nodes<double, 1, true>), grid, dim3(PBLOCK), 0, s, a);
-    else hipLaunchKernelGGL((k_fill_nodes<double, 1, false>), grid, dim3(PBLOCK), 0, s, a);
+    if (two && janus) hipLaunchKernelGGL((k_fill_list<double, 2, true>), grid, dim3(PBLOCK), 0, s, a, fl);
+    else if (two) hipLaunchKernelGGL((k_fill_list<double, 2, false>), grid, dim3(PBLOCK), 0, s, a, fl);
+    else if (janus) hipLaunchKernelGGL((k_fill_list<double, 1, true>), grid, dim3(PBLOCK), 0, s, a, fl);
+    else hipLaunchKernelGGL((k_fill_list<double, 1, false>), grid, dim3(PBLOCK), 0, s, a, fl);
   } else {
-    if (two && janus) hipLaunchKernelGGL((k_fill_nodes<float, 2, true>), grid, dim3(PBLOCK), 0, s, a);
-    else if (two) hipLaunchKernelGGL((k_fill_nodes<float, 2, false>), grid, dim3(PBLOCK), 0, s, a);
-    else if (janus) hipLaunchKernelGGL((k_fill_nodes<float, 1, true>), grid, dim3(PBLOCK), 0, s, a);
-    else hipLaunchKernelGGL((k_fill_nodes<float, 1, false>), grid, dim3(PBLOCK), 0, s, a);
+    if (two && janus) hipLaunchKernelGGL((k_fill_list<float, 2, true>), grid, dim3(PBLOCK), 0, s, a, fl);
+    else if (two) hipLaunchKernelGGL((k_fill_list<float, 2, false>), grid, dim3(PBLOCK), 0, s, a, fl);
+    else if (janus) hipLaunchKernelGGL((k_fill_list<float, 1, true>), grid, dim3(PBLOCK), 0, s, a, fl);
+    else hipLaunchKernelGGL((k_fill_list<float, 1, false>), grid, dim3(PBLOCK), 0, s, a, fl);
   }
   return hipGetLastError();
 }
