@@ -210,7 +210,10 @@ namespace lbh {
 
 void cell_dims(const lb_params& p, int ncell[3]) {
   const int L[3] = {p.nx, p.ny, p.nz};
-  const double side = std::max(1.0, p.hertz_d0);
+  // the neighbouring cells must hold every sphere within the Hertz range, the
+  // lubrication range and 2R + 1/2 (spheres that may share nodes)
+  double side = std::max({1.0, p.hertz_d0, 2.0 * p.radius + 0.5});
+  if (p.lub_mu > 0.0) side = std::max(side, 2.0 * p.radius + p.lub_hn);
   for (int d = 0; d < 3; ++d) ncell[d] = std::max(1, int(std::floor(L[d] / side)));
   if (p.max_particles == 0) ncell[0] = ncell[1] = ncell[2] = 1;
 }
@@ -246,6 +249,14 @@ size_t work_layout(const lb_params& p, WorkLayout& wl, int ncell_total) {
   wl.fcap = std::min<size_t>(wl.fcap, 0xFFFFFFFFu);
   wl.flist = off;
   off = align_up(off + wl.fcap * 2 * sizeof(uint32_t));
+  // Event list: a sphere's created nodes are nodes it owned, its destroyed
+  // nodes nodes it owns now, so at most twice the bound above per sphere.
+  wl.ecount = off;
+  off = align_up(off + sizeof(int32_t));
+  wl.ecap = std::min(N, 2 * size_t(std::max(p.max_particles, 0)) * per);
+  wl.ecap = std::min<size_t>(wl.ecap, 0xFFFFFFFFu);
+  wl.elist = off;
+  off = align_up(off + wl.ecap * 2 * sizeof(uint32_t));
   wl.total = off;
   return off;
 }

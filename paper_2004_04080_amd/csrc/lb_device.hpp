@@ -32,13 +32,14 @@ constexpr int ASTRIDE = 32;             // doubles per sphere in the accumulator
 enum : int {
   PS_X = 0, PS_V = 3, PS_W = 6, PS_Q = 9, PS_FPREV = 13, PS_TPREV = 16,
   PS_XRA = 19,   // centre used for the map of the previous step M_{t-1}
-  PS_XRB = 22,   // centre used for the map two steps back (ping-pong partner)
+  PS_XRB = 22,   // centre used for the map two steps back (kept in the record)
   PS_HAVEPREV = 25
 };
 // per-step accumulators (AoS, ASTRIDE doubles)
 enum : int {
   AC_FLIQ = 0, AC_TLIQ = 3, AC_FLABS = 6, AC_FD = 8, AC_TD = 11, AC_FC = 14, AC_TC = 17,
-  AC_FSC = 20, AC_TSC = 23, AC_FH = 26
+  AC_FSC = 20, AC_TSC = 23, AC_FH = 26,
+  AC_NEAR = 29   // 1 when another sphere's centre is closer than 2R + 1/2 (may share nodes)
 };
 
 // Periodic neighbour addressing of node (x, y, z): index of (x+dx, y+dy, z+dz)

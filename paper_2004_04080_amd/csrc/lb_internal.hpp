@@ -25,6 +25,9 @@ struct WorkLayout {
   size_t fcount = 0;       // int32: entries appended to the frontier list
   size_t flist = 0;        // uint2[fcap]: frontier nodes of the sphere map (node, mask)
   size_t fcap = 0;
+  size_t ecount = 0;       // int32: entries appended to the event list
+  size_t elist = 0;        // uint2[ecap]: node events of a moving step (node, code)
+  size_t ecap = 0;
   size_t total = 0;
 };
 
@@ -119,8 +122,10 @@ hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner);   // walls + all sphe
 hipError_t launch_map_update(lb_ctx* c, hipStream_t s);  // clear, unraster, raster, pairs
 hipError_t launch_events(lb_ctx* c);                     // node creation / destruction
 // frontier list of the sphere map `owner`, whose spheres sit around the
-// centres at record offset `which`, on stream s
-hipError_t launch_frontier(lb_ctx* c, const uint16_t* owner, int which, hipStream_t s);
+// centres at record offset `which`, on stream s; with owner_old set, also
+// the list of node events from owner_old to owner
+hipError_t launch_sphere_lists(lb_ctx* c, const uint16_t* owner, const uint16_t* owner_old,
+                               int which, hipStream_t s);
 // virtual densities (and with forces on, F_SC and T_SC) of the frontier of
 // `owner`; builds the list of the current map first unless list_ready (the
 // list of the new map, built by launch_map_update)

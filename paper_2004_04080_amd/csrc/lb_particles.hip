@@ -80,13 +80,43 @@ struct PArgs {
   double janus_theta0, janus_width, janus_zeta[2];
 };
 
-// Frontier nodes of the sphere map: entries (node, fluid-neighbour mask),
-// count appended so far (cleared before each build), capacity.
-struct FrontierList {
+// A list of nodes built per sphere: entries (node, payload), the count
+// appended so far (cleared before each build) and the capacity.
+struct NodeList {
   uint2* list;
   int32_t* count;
   uint32_t cap;
 };
+
+// LDS staging of list entries: a workgroup moves its entries to the list in
+// blocks, so that the shared counter takes one atomic per block of entries.
+template <int CAP>
+struct Stage {
+  uint2 e[CAP];
+  int staged, base;
+};
+
+template <int CAP>
+__device__ void stage_flush(Stage<CAP>& st, const NodeList& L) {
+  if (threadIdx.x == 0) st.base = atomicAdd(L.count, st.staged);
+  __syncthreads();
+  for (int t = int(threadIdx.x); t < st.staged; t += PBLOCK)
+    if (uint32_t(st.base + t) < L.cap) L.list[st.base + t] = st.e[t];
+  __syncthreads();
+  if (threadIdx.x == 0) st.staged = 0;
+}
+
+// the lanes with `put` append v, one LDS atomic per wave
+template <int CAP>
+__device__ __forceinline__ void stage_push(Stage<CAP>& st, bool put, uint2 v) {
+  const uint64_t has = __ballot(put);
+  if (!has) return;
+  const int lane = __lane_id();
+  int w = 0;
+  if (lane == 0) w = atomicAdd(&st.staged, int(__popcll(has)));
+  w = __shfl(w, 0);
+  if (put) st.e[w + int(__popcll(has & ((1ull << lane) - 1ull)))] = v;
+}
 
 // Sum NV doubles over the workgroup; thread 0 gets the result.
 template <int NV>
@@ -120,18 +150,12 @@ __global__ void k_map_reset(uint16_t* own, uint32_t nx, uint32_t ny, uint32_t nz
   own[n] = (walls && (z == 0 || z == nz - 1)) ? OWN_WALL : 0;
 }
 
-// Clear the nodes that sphere p holds in the map, around the centre at offset `which`.
-__global__ void __launch_bounds__(PBLOCK) k_unraster(PArgs a, int which) {
-  const int p = blockIdx.x;
-  const double* P = a.ps + size_t(p) * PSTRIDE;
-  const double c[3] = {P[which], P[which + 1], P[which + 2]};
-  const Box b = sphere_box(c, a.R);
-  const uint16_t me = uint16_t(p + 1);
-  for_box(b, [&](int x, int y, int z) {
-    const uint32_t n = uint32_t(wrap_box(x, a.nx)) +
-                       uint32_t(a.nx) * (uint32_t(wrap_box(y, a.ny)) + uint32_t(a.ny) * uint32_t(wrap_box(z, a.nz)));
-    if (a.own_new[n] == me) a.own_new[n] = 0;
-  });
+// wall planes z = 0 and z = nz - 1 of a cleared map
+__global__ void k_wall_planes(uint16_t* own, uint32_t nx, uint32_t ny, uint32_t nz) {
+  const uint32_t plane = nx * ny;
+  const uint32_t t = blockIdx.x * PBLOCK + threadIdx.x;
+  if (t >= 2 * plane) return;
+  own[t < plane ? t : size_t(nz - 1) * plane + (t - plane)] = OWN_WALL;
 }
 
 // Lowest sphere index wins a node claimed by several spheres; walls stay walls.
@@ -149,12 +173,16 @@ __device__ __forceinline__ void claim(uint16_t* own, uint32_t n, uint16_t val) {
 }
 
 // Staircase sphere: node n belongs to p when |minimg(r_n - x_p)|^2 < R^2.
-__global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which) {
+// With near_flags, a sphere with no other centre within 2R + 1/2 (AC_NEAR,
+// from k_pairs) shares no node with another sphere and writes its nodes with
+// plain stores into the cleared map; the others claim theirs atomically.
+__global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which, int near_flags) {
   const int p = blockIdx.x;
   const double* P = a.ps + size_t(p) * PSTRIDE;
   const double c[3] = {P[which], P[which + 1], P[which + 2]};
   const Box b = sphere_box(c, a.R);
   const double R2 = a.R * a.R;
+  const bool alone = near_flags && a.acc[size_t(p) * ASTRIDE + AC_NEAR] == 0.0;
   if (which == PS_X && threadIdx.x == 0 && a.flags) {
     // speed limit of the moving-boundary scheme: at most half a node per step
     const double vmax = fmax(fabs(P[PS_V]), fmax(fabs(P[PS_V + 1]), fabs(P[PS_V + 2])));
@@ -166,8 +194,11 @@ __global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which) {
     const double dx = min_image(wx - c[0], a.L[0]);
     const double dy = min_image(wy - c[1], a.L[1]);
     const double dz = min_image(wz - c[2], a.L[2]);
-    if (dx * dx + dy * dy + dz * dz < R2)
-      claim(a.own_new, uint32_t(wx) + a.nx * (uint32_t(wy) + a.ny * uint32_t(wz)), uint16_t(p + 1));
+    if (dx * dx + dy * dy + dz * dz < R2) {
+      const uint32_t n = uint32_t(wx) + a.nx * (uint32_t(wy) + a.ny * uint32_t(wz));
+      if (alone) a.own_new[n] = uint16_t(p + 1);
+      else claim(a.own_new, n, uint16_t(p + 1));
+    }
   });
 }
 
@@ -179,84 +210,101 @@ __global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which) {
 // maps, and the sphere it left loses the momentum sum_k rho_bar_k u_w. Both
 // are summed per sphere into F_d, T_d, F_c, T_c (wave-segmented sums, then
 // FP64 atomics; the accumulators are cleared at the start of the step).
+// One node event: node n destroyed (fluid -> sphere `sphere`) or created
+// (sphere `sphere` -> fluid); its momentum terms go to v (for sphere pid).
 template <typename real, int NC>
-__global__ void __launch_bounds__(PBLOCK) k_events(PArgs a) {
-  const uint32_t n = blockIdx.x * PBLOCK + threadIdx.x;
-  int pid = -1;
-  double v[12];
+__device__ __forceinline__ void event_one(const PArgs& a, uint32_t n, bool destroyed, int sphere,
+                                          int& pid, double v[12]) {
+  pid = sphere;
+  const double* P = a.ps + size_t(pid) * PSTRIDE;
+  uint32_t x, y, z;
+  node_xyz(n, uint32_t(a.nx), uint32_t(a.ny), x, y, z);
+  Nbr nb(x, y, z, uint32_t(a.nx), uint32_t(a.ny), uint32_t(a.nz));
+  const double d[3] = {min_image(double(x) - P[PS_X], a.L[0]),
+                       min_image(double(y) - P[PS_X + 1], a.L[1]),
+                       min_image(double(z) - P[PS_X + 2], a.L[2])};
+  real* fin = static_cast<real*>(a.fin);
+  real* psi = static_cast<real*>(a.psi);
+  const uint32_t N = a.N;
+  if (destroyed) {
+    double J[3] = {0, 0, 0};
 #pragma unroll
-  for (int c = 0; c < 12; ++c) v[c] = 0.0;
-  const uint16_t o = n < a.N ? a.own_old[n] : uint16_t(0);
-  const uint16_t w = n < a.N ? a.own_new[n] : uint16_t(0);
-  const bool destroyed = o == 0 && w != 0 && w != OWN_WALL;
-  const bool created = w == 0 && o != 0 && o != OWN_WALL;
-  if (destroyed || created) {
-    pid = int(destroyed ? w : o) - 1;
-    const double* P = a.ps + size_t(pid) * PSTRIDE;
-    uint32_t x, y, z;
-    node_xyz(n, uint32_t(a.nx), uint32_t(a.ny), x, y, z);
-    Nbr nb(x, y, z, uint32_t(a.nx), uint32_t(a.ny), uint32_t(a.nz));
-    const double d[3] = {min_image(double(x) - P[PS_X], a.L[0]),
-                         min_image(double(y) - P[PS_X + 1], a.L[1]),
-                         min_image(double(z) - P[PS_X + 2], a.L[2])};
-    real* fin = static_cast<real*>(a.fin);
-    real* psi = static_cast<real*>(a.psi);
-    const uint32_t N = a.N;
-    if (destroyed) {
-      double J[3] = {0, 0, 0};
-      for (int k = 0; k < NC; ++k)
+    for (int k = 0; k < NC; ++k)
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const double fv = double(fin[(size_t(k) * Q + i) * N + nb.pull(i)]);
-          J[0] += fv * CX[i];
-          J[1] += fv * CY[i];
-          J[2] += fv * CZ[i];
-        }
-      v[0] = J[0];
-      v[1] = J[1];
-      v[2] = J[2];
-      v[3] = d[1] * J[2] - d[2] * J[1];
-      v[4] = d[2] * J[0] - d[0] * J[2];
-      v[5] = d[0] * J[1] - d[1] * J[0];
-    } else {
-      const double wx_ = P[PS_W], wy_ = P[PS_W + 1], wz_ = P[PS_W + 2];
-      const double uw[3] = {P[PS_V] + (wy_ * d[2] - wz_ * d[1]),
-                            P[PS_V + 1] + (wz_ * d[0] - wx_ * d[2]),
-                            P[PS_V + 2] + (wx_ * d[1] - wy_ * d[0])};
-      double wsum = 0.0, s[NC];
-      for (int k = 0; k < NC; ++k) s[k] = 0.0;
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const uint32_t m = nb.push(i);
-        if (a.own_old[m] != 0 || a.own_new[m] != 0) continue;
-        wsum += WQ[i];
-        for (int k = 0; k < NC; ++k) s[k] += WQ[i] * double(psi[size_t(k) * N + m]);
+      for (int i = 0; i < Q; ++i) {
+        const double fv = double(fin[(size_t(k) * Q + i) * N + nb.pull(i)]);
+        J[0] += fv * CX[i];
+        J[1] += fv * CY[i];
+        J[2] += fv * CZ[i];
       }
-      const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
-      double tot = 0.0;
-      for (int k = 0; k < NC; ++k) {
-        // deviation of the created density from rho0_k
-        const double dr = wsum > 0.0 ? s[k] / wsum : a.rho_fb[k] - a.rho0[k];
-        const double rb = a.rho0[k] + dr;
-        tot += rb;
+    v[0] = J[0];
+    v[1] = J[1];
+    v[2] = J[2];
+    v[3] = d[1] * J[2] - d[2] * J[1];
+    v[4] = d[2] * J[0] - d[0] * J[2];
+    v[5] = d[0] * J[1] - d[1] * J[0];
+  } else {
+    const double wx_ = P[PS_W], wy_ = P[PS_W + 1], wz_ = P[PS_W + 2];
+    const double uw[3] = {P[PS_V] + (wy_ * d[2] - wz_ * d[1]),
+                          P[PS_V + 1] + (wz_ * d[0] - wx_ * d[2]),
+                          P[PS_V + 2] + (wx_ * d[1] - wy_ * d[0])};
+    double wsum = 0.0, s[NC];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const double cu = CX[i] * uw[0] + CY[i] * uw[1] + CZ[i] * uw[2];
-          fin[(size_t(k) * Q + i) * N + nb.pull(i)] =
-              real(WQ[i] * dr + WQ[i] * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-        }
-        psi[size_t(k) * N + n] = real(dr);
-      }
-      const double M[3] = {tot * uw[0], tot * uw[1], tot * uw[2]};
-      v[6] = -M[0];
-      v[7] = -M[1];
-      v[8] = -M[2];
-      v[9] = -(d[1] * M[2] - d[2] * M[1]);
-      v[10] = -(d[2] * M[0] - d[0] * M[2]);
-      v[11] = -(d[0] * M[1] - d[1] * M[0]);
+    for (int k = 0; k < NC; ++k) s[k] = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const uint32_t m = nb.push(i);
+      if (a.own_old[m] != 0 || a.own_new[m] != 0) continue;
+      wsum += WQ[i];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) s[k] += WQ[i] * double(psi[size_t(k) * N + m]);
     }
+    const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+    double tot = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      // deviation of the created density from rho0_k
+      const double dr = wsum > 0.0 ? s[k] / wsum : a.rho_fb[k] - a.rho0[k];
+      const double rb = a.rho0[k] + dr;
+      tot += rb;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const double cu = CX[i] * uw[0] + CY[i] * uw[1] + CZ[i] * uw[2];
+        fin[(size_t(k) * Q + i) * N + nb.pull(i)] =
+            real(WQ[i] * dr + WQ[i] * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+      }
+      psi[size_t(k) * N + n] = real(dr);
+    }
+    const double M[3] = {tot * uw[0], tot * uw[1], tot * uw[2]};
+    v[6] = -M[0];
+    v[7] = -M[1];
+    v[8] = -M[2];
+    v[9] = -(d[1] * M[2] - d[2] * M[1]);
+    v[10] = -(d[2] * M[0] - d[0] * M[2]);
+    v[11] = -(d[0] * M[1] - d[1] * M[0]);
   }
-  flush_runs<12>(a.acc, AC_FD, pid, v);
+}
+
+template <typename real, int NC>
+__global__ void __launch_bounds__(PBLOCK) k_events_list(PArgs a, NodeList ev) {
+  const uint32_t total = min(uint32_t(*ev.count), ev.cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && uint32_t(*ev.count) > ev.cap && a.flags)
+    atomicOr(a.flags + 2, 1);  // list overflow (the capacity bound rules it out)
+  const uint32_t nwaves = gridDim.x * (PBLOCK / 64);
+  // whole waves step together through the list: flush_runs needs every lane
+  for (uint32_t base = (blockIdx.x * PBLOCK + threadIdx.x) / 64 * 64; base < total;
+       base += nwaves * 64) {
+    const uint32_t e = base + __lane_id();
+    int pid = -1;
+    double v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = 0.0;
+    if (e < total) {
+      const uint2 en = ev.list[e];
+      event_one<real, NC>(a, en.x, (en.y >> 31) != 0u, int(en.y & 0xFFFFu) - 1, pid, v);
+    }
+    flush_runs<12>(a.acc, AC_FD, pid, v);
+  }
 }
 
 // Direction sets as bit masks over the 18 moving directions: axis and
@@ -276,71 +324,88 @@ constexpr uint32_t kNeg1[3] = {dir_set(0, -1, 1), dir_set(1, -1, 1), dir_set(2, 
 constexpr uint32_t kPos2[3] = {dir_set(0, 1, 2), dir_set(1, 1, 2), dir_set(2, 1, 2)};
 constexpr uint32_t kNeg2[3] = {dir_set(0, -1, 2), dir_set(1, -1, 2), dir_set(2, -1, 2)};
 
-// Frontier list of a sphere map: every node of a sphere with at least one
-// fluid neighbour, as (node, mask of the directions i with n + c_i fluid).
+// Lists of a sphere map, one workgroup per sphere over its box:
+// * frontier: every node of the sphere with at least one fluid neighbour, as
+//   (node, mask of the directions i with n + c_i fluid);
+// * with ev.list set, the node events of the step from own_old to own_new:
+//   (node, sphere + 1, bit 31 set for a destroyed node). A destroyed node is
+//   listed by the sphere that takes it, a created one by the sphere that
+//   leaves it; the box then also covers the sphere's previous centre (PS_XRA),
+//   up to 4 nodes away (a sphere that moved further has raised the speed flag).
 // The map holds sphere p around the centre at offset `which` of its record.
-// One workgroup per sphere walks its box and appends the nodes the sphere
-// owns, a wave at a time, so the entries of one sphere sit together. Along
-// an axis shorter than the box, one period of the box is walked, so that no
-// node is listed twice.
-__global__ void __launch_bounds__(PBLOCK) k_frontier(PArgs a, FrontierList fl, int which) {
-  // entries are staged in LDS and moved to the list in blocks, so that the
-  // shared counter takes one atomic per block of entries, not one per wave
-  constexpr int STAGE = 1024;
-  __shared__ uint2 stage[STAGE];
-  __shared__ int staged, base;
+// Entries of one sphere sit together in each list. Along an axis shorter than
+// the box, one period of the box is walked, so that no node is listed twice.
+__global__ void __launch_bounds__(PBLOCK) k_sphere_lists(PArgs a, NodeList fl, NodeList ev,
+                                                         int which) {
+  __shared__ Stage<1024> sf;
+  __shared__ Stage<512> se;
+  const bool events = ev.list != nullptr;
   const int p = blockIdx.x;
   const double* P = a.ps + size_t(p) * PSTRIDE;
   const double c[3] = {P[which], P[which + 1], P[which + 2]};
-  const Box b = sphere_box(c, a.R);
+  Box b = sphere_box(c, a.R);
+  if (events && b.total > 0) {
+    const int L[3] = {a.nx, a.ny, a.nz};
+    for (int d = 0; d < 3; ++d) {
+      double dd = min_image(P[PS_XRA + d] - c[d], double(L[d]));
+      dd = isfinite(dd) ? fmin(4.0, fmax(-4.0, dd)) : 0.0;
+      const int lo = int(floor(c[d] + dd - a.R)), hi = int(ceil(c[d] + dd + a.R));
+      const int nlo = min(b.lo[d], lo), nhi = max(b.lo[d] + b.n[d] - 1, hi);
+      b.lo[d] = nlo;
+      b.n[d] = nhi - nlo + 1;
+    }
+  }
   const int nb0 = min(b.n[0], a.nx), nb1 = min(b.n[1], a.ny), nb2 = min(b.n[2], a.nz);
   const uint16_t me = uint16_t(p + 1);
   const int tx = int(threadIdx.x & 15u), ty = int(threadIdx.x >> 4);
-  const int lane = __lane_id();
-  if (threadIdx.x == 0) staged = 0;
-  auto flush = [&]() {
-    if (threadIdx.x == 0) base = atomicAdd(fl.count, staged);
-    __syncthreads();
-    for (int t = int(threadIdx.x); t < staged; t += PBLOCK)
-      if (uint32_t(base + t) < fl.cap) fl.list[base + t] = stage[t];
-    __syncthreads();
-    if (threadIdx.x == 0) staged = 0;
-  };
+  const double deep2 = a.R > 1.5 ? (a.R - 1.5) * (a.R - 1.5) : -1.0;
+  if (threadIdx.x == 0) sf.staged = se.staged = 0;
   // trip counts are uniform over the workgroup: every thread reaches the barriers
   for (int k = 0; k < nb2; ++k)
     for (int jb = 0; jb < nb1; jb += 16)
       for (int ib = 0; ib < nb0; ib += 16) {
         const int i = ib + tx, j = jb + ty;
-        uint32_t n = 0, mask = 0;
+        uint32_t n = 0, mask = 0, evc = 0;
         if (i < nb0 && j < nb1) {
           const uint32_t wx = uint32_t(wrap_box(b.lo[0] + i, a.nx));
           const uint32_t wy = uint32_t(wrap_box(b.lo[1] + j, a.ny));
           const uint32_t wz = uint32_t(wrap_box(b.lo[2] + k, a.nz));
           n = wx + uint32_t(a.nx) * (wy + uint32_t(a.ny) * wz);
-          if (a.own_new[n] == me) {
+          const uint16_t w = a.own_new[n];
+          // a node closer than R - 3/2 to the centre has every neighbour (at
+          // most sqrt 2 away) inside the ball: none of them is fluid
+          const double dx = min_image(double(wx) - c[0], a.L[0]);
+          const double dy = min_image(double(wy) - c[1], a.L[1]);
+          const double dz = min_image(double(wz) - c[2], a.L[2]);
+          if (w == me && !(dx * dx + dy * dy + dz * dz < deep2)) {
             Nbr nbr(wx, wy, wz, uint32_t(a.nx), uint32_t(a.ny), uint32_t(a.nz));
 #pragma unroll
             for (int d = 1; d < Q; ++d)
               if (a.own_new[nbr.push(d)] == 0) mask |= 1u << d;
           }
+          if (events) {
+            const uint16_t o = a.own_old[n];
+            if (o == 0 && w == me) evc = 0x80000000u | me;   // destroyed
+            else if (w == 0 && o == me) evc = me;           // created
+          }
         }
         __syncthreads();
-        const int cur = staged;  // the same value in every thread
+        const int cf = sf.staged, ce = se.staged;  // the same values in every thread
         __syncthreads();
-        if (cur > STAGE - PBLOCK) {  // room for one entry per thread
-          flush();
+        if (cf > 1024 - PBLOCK) {  // room for one entry per thread
+          stage_flush(sf, fl);
           __syncthreads();
         }
-        const uint64_t has = __ballot(mask != 0);
-        if (has) {
-          int w = 0;
-          if (lane == 0) w = atomicAdd(&staged, int(__popcll(has)));
-          w = __shfl(w, 0);
-          if (mask != 0) stage[w + int(__popcll(has & ((1ull << lane) - 1ull)))] = make_uint2(n, mask);
+        if (ce > 512 - PBLOCK) {
+          stage_flush(se, ev);
+          __syncthreads();
         }
+        stage_push(sf, mask != 0, make_uint2(n, mask));
+        if (events) stage_push(se, evc != 0, make_uint2(n, evc));
       }
   __syncthreads();
-  if (staged > 0) flush();
+  if (sf.staged > 0) stage_flush(sf, fl);
+  if (events && se.staged > 0) stage_flush(se, ev);
 }
 
 // Virtual densities on the sphere frontier (Eq. soliddens) and the Shan-Chen
@@ -351,7 +416,7 @@ __global__ void __launch_bounds__(PBLOCK) k_frontier(PArgs a, FrontierList fl, i
 // torque about the sphere centre are summed into F_SC, T_SC of its sphere.
 // Wall nodes are left to the wall fill.
 //
-// The frontier nodes come from a list (k_frontier), one thread per entry, so
+// The frontier nodes come from a list (k_sphere_lists), one thread per entry, so
 // that the waves are full: walking every node of the box instead leaves most
 // lanes of a wave idle, since a wave crossing a sphere holds a handful of its
 // frontier nodes among fluid and interior nodes.
@@ -449,7 +514,7 @@ __device__ __forceinline__ void fill_one(const PArgs& a, uint32_t n, uint32_t ma
 }
 
 template <typename real, int NC, bool JANUS>
-__global__ void __launch_bounds__(PBLOCK) k_fill_list(PArgs a, FrontierList fl) {
+__global__ void __launch_bounds__(PBLOCK) k_fill_list(PArgs a, NodeList fl) {
   const uint32_t total = min(uint32_t(*fl.count), fl.cap);
   if (blockIdx.x == 0 && threadIdx.x == 0 && uint32_t(*fl.count) > fl.cap && a.flags)
     atomicOr(a.flags + 2, 1);  // list overflow (the capacity bound rules it out)
@@ -508,29 +573,44 @@ __global__ void k_cell_count(CellArgs a) {
   atomicAdd(&a.count[cell_of(a, a.ps + size_t(p) * PSTRIDE)], 1);
 }
 
-// exclusive scan of count into start (single workgroup), then clear count
+// exclusive scan of count into start (single workgroup), then clear count;
+// tiles of 8 consecutive cells per thread keep the serial rounds few
 __global__ void __launch_bounds__(1024) k_cell_scan(int32_t* count, int32_t* start, int ncell) {
-  __shared__ int32_t sh[1024];
+  constexpr int PER = 8, TILE = 1024 * PER;
+  __shared__ int32_t wsum[16];
   __shared__ int32_t carry;
+  const int lane = __lane_id(), wv = int(threadIdx.x) / 64;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  for (int base = 0; base < ncell; base += 1024) {
-    const int i = base + threadIdx.x;
-    const int32_t v = i < ncell ? count[i] : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += t;
-      __syncthreads();
+  for (int base = 0; base < ncell; base += TILE) {
+    const int i0 = base + int(threadIdx.x) * PER;
+    int32_t v[PER], t = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      v[j] = i0 + j < ncell ? count[i0 + j] : 0;
+      t += v[j];
     }
-    if (i < ncell) {
-      start[i] = carry + sh[threadIdx.x] - v;
-      count[i] = 0;
+    // inclusive scan of the thread totals within the wave, then over waves
+    int incl = t;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(incl, off);
+      if (lane >= off) incl += u;
     }
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    if (threadIdx.x == 1023) carry += sh[1023];
+    int before = carry;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    int run = before + incl - t;
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      if (i0 + j < ncell) {
+        start[i0 + j] = run;
+        count[i0 + j] = 0;
+        run += v[j];
+      }
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = run;
     __syncthreads();
   }
   if (threadIdx.x == 0) start[ncell] = carry;
@@ -577,6 +657,7 @@ __global__ void k_pairs(CellArgs a) {
   int ci[3];
   for (int d = 0; d < 3; ++d) ci[d] = cell_index(xp[d], a.cs[d], a.nc[d]);
   double F[3] = {0, 0, 0};
+  bool near = false;  // another centre closer than 2R + 1/2: the two may share nodes
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
     // visit each neighbouring cell once, also when there are fewer than 3 cells
@@ -596,6 +677,7 @@ __global__ void k_pairs(CellArgs a) {
           const double d[3] = {min_image(xq[0] - xp[0], a.L[0]), min_image(xq[1] - xp[1], a.L[1]),
                                min_image(xq[2] - xp[2], a.L[2])};
           const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          near = near || !(r >= 2.0 * a.R + 0.5);
           const double mag = hertz_mag(r, a.K, a.d0, a.rcap);
           if (mag != 0.0)
             for (int e = 0; e < 3; ++e) F[e] -= mag * d[e] / r;
@@ -619,6 +701,7 @@ __global__ void k_pairs(CellArgs a) {
   }
   double* A = a.acc + size_t(p) * ASTRIDE;
   for (int e = 0; e < 3; ++e) A[AC_FH + e] = F[e];
+  A[AC_NEAR] = near ? 1.0 : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -742,7 +825,7 @@ hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner) {
                      owner, g.nx, g.ny, g.nz, c->P.walls);
   if (c->nparticles > 0)
     hipLaunchKernelGGL(k_raster, dim3(c->nparticles), dim3(PBLOCK), 0, c->stream,
-                       pargs(c, owner, owner), int(PS_X));
+                       pargs(c, owner, owner), int(PS_X), 0);
   return hipGetLastError();
 }
 
@@ -760,10 +843,6 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   const PArgs a = pargs(c, own_new, own_old);
   const dim3 gp(c->nparticles), bp(PBLOCK);
   hipError_t e0 = hipMemsetAsync(pacc(c), 0, size_t(c->nparticles) * ASTRIDE * sizeof(double), s);
-  if (e0 != hipSuccess) return e0;
-  hipLaunchKernelGGL(k_unraster, gp, bp, 0, s, a, int(PS_XRB));
-  hipLaunchKernelGGL(k_raster, gp, bp, 0, s, a, int(PS_X));
-  e0 = launch_frontier(c, own_new, int(PS_X), s);
   if (e0 != hipSuccess) return e0;
   // Hertz pairs through the cell list
   CellArgs ca;
@@ -798,54 +877,78 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_fill, gt, bp, 0, s, ca);
   hipLaunchKernelGGL(k_cell_sort, dim3((ncell + PBLOCK - 1) / PBLOCK), bp, 0, s, ca, ncell);
   hipLaunchKernelGGL(k_pairs, gt, bp, 0, s, ca);
-  return hipGetLastError();
+  // the new map: cleared, walls, spheres at the current centres
+  e = hipMemsetAsync(own_new, 0, size_t(c->geo.N) * sizeof(uint16_t), s);
+  if (e != hipSuccess) return e;
+  if (c->P.walls) {
+    const uint32_t plane = c->geo.nx * c->geo.ny;
+    hipLaunchKernelGGL(k_wall_planes, dim3((2 * plane + PBLOCK - 1) / PBLOCK), bp, 0, s, own_new,
+                       c->geo.nx, c->geo.ny, c->geo.nz);
+  }
+  hipLaunchKernelGGL(k_raster, gp, bp, 0, s, a, int(PS_X), 1);
+  return launch_sphere_lists(c, own_new, own_old, int(PS_X), s);
 }
 
 // Node creation and destruction between the two maps (after the density pass
 // and the map update).
-hipError_t launch_events(lb_ctx* c) {
-  uint16_t* own_new = static_cast<uint16_t*>(c->B.owner[1 - c->own_old]);
-  const uint16_t* own_old = static_cast<const uint16_t*>(c->B.owner[c->own_old]);
-  const PArgs a = pargs(c, own_new, own_old);
-  const dim3 gn((c->geo.N + PBLOCK - 1) / PBLOCK), bp(PBLOCK);
-  const bool two = c->geo.ncomp == 2;
-  if (c->geo.prec == LB_FP64) {
-    if (two) hipLaunchKernelGGL((k_events<double, 2>), gn, bp, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_events<double, 1>), gn, bp, 0, c->stream, a);
-  } else {
-    if (two) hipLaunchKernelGGL((k_events<float, 2>), gn, bp, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_events<float, 1>), gn, bp, 0, c->stream, a);
-  }
-  return hipGetLastError();
-}
-
-static FrontierList frontier_list(lb_ctx* c) {
-  FrontierList fl;
+static NodeList frontier_list(lb_ctx* c) {
+  NodeList fl;
   fl.list = reinterpret_cast<uint2*>(wptr(c, c->wl.flist));
   fl.count = reinterpret_cast<int32_t*>(wptr(c, c->wl.fcount));
   fl.cap = uint32_t(c->wl.fcap);
   return fl;
 }
 
-hipError_t launch_frontier(lb_ctx* c, const uint16_t* owner, int which, hipStream_t s) {
-  const FrontierList fl = frontier_list(c);
-  const hipError_t e = hipMemsetAsync(fl.count, 0, sizeof(int32_t), s);
+static NodeList event_list(lb_ctx* c) {
+  NodeList ev;
+  ev.list = reinterpret_cast<uint2*>(wptr(c, c->wl.elist));
+  ev.count = reinterpret_cast<int32_t*>(wptr(c, c->wl.ecount));
+  ev.cap = uint32_t(c->wl.ecap);
+  return ev;
+}
+
+hipError_t launch_sphere_lists(lb_ctx* c, const uint16_t* owner, const uint16_t* owner_old,
+                               int which, hipStream_t s) {
+  const NodeList fl = frontier_list(c);
+  NodeList ev = event_list(c);
+  hipError_t e = hipMemsetAsync(fl.count, 0, sizeof(int32_t), s);
+  if (e == hipSuccess && owner_old) e = hipMemsetAsync(ev.count, 0, sizeof(int32_t), s);
   if (e != hipSuccess) return e;
+  if (!owner_old) ev.list = nullptr;
   if (c->nparticles > 0)
-    hipLaunchKernelGGL(k_frontier, dim3(c->nparticles), dim3(PBLOCK), 0, s,
-                       pargs(c, const_cast<uint16_t*>(owner), owner), fl, which);
+    hipLaunchKernelGGL(k_sphere_lists, dim3(c->nparticles), dim3(PBLOCK), 0, s,
+                       pargs(c, const_cast<uint16_t*>(owner), owner_old ? owner_old : owner), fl,
+                       ev, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_events(lb_ctx* c) {
+  uint16_t* own_new = static_cast<uint16_t*>(c->B.owner[1 - c->own_old]);
+  const uint16_t* own_old = static_cast<const uint16_t*>(c->B.owner[c->own_old]);
+  const PArgs a = pargs(c, own_new, own_old);
+  const NodeList ev = event_list(c);
+  if (ev.cap == 0) return hipSuccess;
+  const dim3 grid(uint32_t(std::min<size_t>((c->wl.ecap + PBLOCK - 1) / PBLOCK, 1024))), bp(PBLOCK);
+  const bool two = c->geo.ncomp == 2;
+  if (c->geo.prec == LB_FP64) {
+    if (two) hipLaunchKernelGGL((k_events_list<double, 2>), grid, bp, 0, c->stream, a, ev);
+    else hipLaunchKernelGGL((k_events_list<double, 1>), grid, bp, 0, c->stream, a, ev);
+  } else {
+    if (two) hipLaunchKernelGGL((k_events_list<float, 2>), grid, bp, 0, c->stream, a, ev);
+    else hipLaunchKernelGGL((k_events_list<float, 1>), grid, bp, 0, c->stream, a, ev);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces, bool list_ready) {
   if (!list_ready) {
     // the current map: rasterised around the centres of the last step
-    const hipError_t e = launch_frontier(c, owner, int(PS_XRA), c->stream);
+    const hipError_t e = launch_sphere_lists(c, owner, nullptr, int(PS_XRA), c->stream);
     if (e != hipSuccess) return e;
   }
   PArgs a = pargs(c, const_cast<uint16_t*>(owner), owner);
   if (!forces) a.acc = nullptr;  // psi only: leave the force terms alone
-  const FrontierList fl = frontier_list(c);
+  const NodeList fl = frontier_list(c);
   if (fl.cap == 0) return hipSuccess;
   // enough waves to cover the list in a few passes
   const dim3 grid(uint32_t(std::min<size_t>((c->wl.fcap + PBLOCK - 1) / PBLOCK, 8192)));
