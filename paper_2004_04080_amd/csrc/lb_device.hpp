@@ -90,6 +90,24 @@ __device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
                                      idx * uint32_t(sizeof(T)));
 }
+// Raw buffer access through a descriptor in scalar registers: the base of
+// one array (uniform), its size in bytes and a 32-bit byte offset per lane.
+// An offset at or past the size is out of range: the hardware drops such a
+// store (gfx9 raw-buffer range check), which predicates a store without a
+// branch or a change of the execution mask. kOffNone is out of range for every
+// array here (a population plane holds at most 0xFFFFFFFC bytes).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+constexpr uint32_t kOffNone = 0xFFFFFFFFu;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), short(0), int(bytes), 0x00020000);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(off), 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, int(off), 0, 0);
+}
+
 template <typename T>
 __device__ __forceinline__ void st32(T* base, uint32_t idx, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T))) = v;

@@ -474,7 +474,13 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
     const real wB[2] = {real(W1) * B, real(W2) * B};
     real* fk = fout + size_t(k) * Q * N;
     auto put = [&](int i, real v) {
-      if (smask & (1u << i)) st32(fk + size_t(i) * N, n, fluid ? v : real(0));
+      // with spheres the store is predicated per lane and direction: by an
+      // out-of-range offset, without a branch
+      if (SOLIDS)
+        buf_store(buf_rsrc(fk + size_t(i) * N, N * uint32_t(sizeof(real))),
+                  ((smask >> i) & 1u) ? n * uint32_t(sizeof(real)) : kOffNone, fluid ? v : real(0));
+      else if (smask & (1u << i))
+        st32(fk + size_t(i) * N, n, v);
       // the link's post-collision value, for the lane that will take the link
       if (kDenseLinks<real>) {
         if (SOLIDS) lq.fs[k][i * 64 + lane] = v;
