@@ -629,6 +629,7 @@ int lb_set_state(lb_ctx* c, const void* blob, size_t bytes) {
     HIPCHK(c, hipMemcpy(c->B.owner[1 - c->own_old], in, ob, hipMemcpyHostToDevice));
     in += ob;
   }
+  c->flist_map = nullptr;
   if (pb) HIPCHK(c, hipMemcpy(pstate(c), in, pb, hipMemcpyHostToDevice));
   c->nparticles = h.nparticles;
   c->moving = h.nparticles > 0 && !c->P.particles_fixed;

@@ -68,6 +68,9 @@ struct lb_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   void* fft = nullptr;  // FFT plan of the domain-size measure, made on first use
+  // the owner map the frontier list was built for (null: none); every write
+  // of a map other than the map update, which rebuilds the list, clears it
+  const void* flist_map = nullptr;
   lbh::Geometry geo;
   lbh::WorkLayout wl;
   lbh::AdjLayout al;

@@ -821,6 +821,7 @@ static PArgs pargs(lb_ctx* c, uint16_t* own_new, const uint16_t* own_old) {
 
 hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner) {
   const auto& g = c->geo;
+  c->flist_map = nullptr;
   hipLaunchKernelGGL(k_map_reset, dim3((g.N + PBLOCK - 1) / PBLOCK), dim3(PBLOCK), 0, c->stream,
                      owner, g.nx, g.ny, g.nz, c->P.walls);
   if (c->nparticles > 0)
@@ -886,7 +887,9 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
                        c->geo.nx, c->geo.ny, c->geo.nz);
   }
   hipLaunchKernelGGL(k_raster, gp, bp, 0, s, a, int(PS_X), 1);
-  return launch_sphere_lists(c, own_new, own_old, int(PS_X), s);
+  e = launch_sphere_lists(c, own_new, own_old, int(PS_X), s);
+  c->flist_map = e == hipSuccess ? own_new : nullptr;
+  return e;
 }
 
 // Node creation and destruction between the two maps (after the density pass
@@ -941,10 +944,11 @@ hipError_t launch_events(lb_ctx* c) {
 }
 
 hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces, bool list_ready) {
-  if (!list_ready) {
+  if (!list_ready && c->flist_map != owner) {
     // the current map: rasterised around the centres of the last step
     const hipError_t e = launch_sphere_lists(c, owner, nullptr, int(PS_XRA), c->stream);
     if (e != hipSuccess) return e;
+    c->flist_map = owner;
   }
   PArgs a = pargs(c, const_cast<uint16_t*>(owner), owner);
   if (!forces) a.acc = nullptr;  // psi only: leave the force terms alone
