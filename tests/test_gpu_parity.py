@@ -154,6 +154,51 @@ def test_moving_spheres_fp32_step_parity():
         assert ep["x"] < 1e-6
 
 
+@pytest.mark.parametrize("walls", [False, True])
+def test_one_component_moving_spheres_fp64(walls):
+    """A single fluid with moving spheres (no Shan-Chen force): the
+    one-component collide, fill and node events against the oracle."""
+    shape = (26, 22, 24)
+    w, x, v, om = _spheres(shape, 6, 3.0, synth.BASE_SEED + 28, walls)
+    rho = w.densities()[:1]
+    kw = dict(ncomp=1, tau=(0.8, 0.8), radius=3.0, particle_density=2.0, g=(1e-5, 0.0, -2e-5))
+    if walls:
+        kw.update(walls=True, wall_u_lo=(0.01, 0, 0), wall_u_hi=(-0.01, 0, 0))
+    o, lat = make_pair(shape, rho, x=x, v=v, w=om, **kw)
+    done = 0
+    events = 0
+    for h in (1, 5, 20):
+        own0 = o.owner()
+        assert o.step(h - done) == 0
+        lat.step(h - done)
+        events += int((own0 != o.owner()).sum())
+        done = h
+        _check(o, lat, 1e-11, f"one-component spheres t={h}", df_gate=h <= 10)
+        ep = compare_particles(o, lat)
+        print("particles", {k: f"{v:.1e}" for k, v in ep.items()}, flush=True)
+        assert ep["x"] < 1e-11 and ep["v"] < 1e-11 and ep["w"] < 1e-11
+        for k in ("Fliq", "Tliq", "Fd", "Td", "Fc", "Tc", "FH"):
+            assert ep[k] < 1e-12, k
+    assert events > 0
+
+
+def test_one_component_moving_spheres_fp32_step_parity():
+    shape = (30, 28, 26)
+    w, x, v, om = _spheres(shape, 8, 3.5, synth.BASE_SEED + 29)
+    o, lat = make_pair(shape, w.densities()[:1], x=x, v=v, w=om, precision="fp32", ncomp=1,
+                       tau=(0.9, 0.9), radius=3.5, particle_density=2.0)
+    lat.step(20)
+    sync_state(o, lat)
+    for t in range(3):
+        o.step(1)
+        lat.step(1)
+        _check(o, lat, TOL32, f"fp32 one-component spheres step {t}", tol_u=TOL32_U)
+        ep = compare_particles(o, lat)
+        for k in ("Fliq", "Tliq", "Fd", "Fc"):
+            assert ep[k] < 1e-5, k
+        assert ep["x"] < 1e-6
+
+
 def test_fixed_spheres_fp64_and_loss():
     shape = (20, 18, 16)
     w, x, _, _ = _spheres(shape, 3, 3.0, synth.BASE_SEED + 27)
