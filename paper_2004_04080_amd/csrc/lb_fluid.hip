@@ -399,11 +399,11 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
     }
   }
 
-  // Solid lanes run the same arithmetic on whatever they gathered and store
-  // zeros through the same store instructions as the fluid lanes, into slot 0
-  // and the slots towards solid neighbours; the slots towards fluid neighbours
-  // are left to the reflections written by those neighbours. A wave that
-  // mixes fluid and solid nodes thus issues every store once.
+  // Solid lanes run the same arithmetic and store zeros through the same
+  // store instructions as the fluid lanes, into slot 0 and the slots towards
+  // solid neighbours; the slots towards fluid neighbours are left to the
+  // reflections written by those neighbours. A wave that mixes fluid and
+  // solid nodes thus issues every store once.
   const uint32_t smask = !valid ? 0u : (fluid ? 0x7FFFFu : (lmask | 1u));
   if (!fluid) lmask = 0;  // links are walked from fluid nodes only
 
@@ -423,7 +423,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
       for (int e = 0; e < 3; ++e)
         if (c[e]) j[e] += c[e] > 0 ? d : -d;
     }
-    drho[k] = s;
+    drho[k] = (SOLIDS && !fluid) ? real(0) : s;
     rho[k] = real(a.rho0[k]) + s;
     jx[k] = j[0];
     jy[k] = j[1];
@@ -452,7 +452,15 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
     const real nub = real(1) / inv_nu;
     om = real(2.0 / 3.0) / (real(2) * nub + real(1.0 / 3.0));
   }
-  const real omc = real(1) - om;
+  // A solid lane relaxes with omega = 0 from zero density deviation, velocity
+  // and acceleration: each of its outputs is then 0 * f + 0 (f is a finite
+  // value gathered from slots that every step writes), so it stores zeros
+  // without a select per output.
+  if (SOLIDS && !fluid) {
+    ux = uy = uz = real(0);
+    om = real(0);
+  }
+  const real omc = (SOLIDS && !fluid) ? real(0) : real(1) - om;
   const real ouu = omc * (ux * ux + uy * uy + uz * uz);
   // (1 - omega) c.u and (1 - omega)(c.u)^2 per pair, shared by the components
   real ocu[Q], ocu2[Q];
@@ -466,7 +474,9 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
   const bool enq = SOLIDS && queued && lmask != 0;
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    const real vx = ux + ax[k], vy = uy + ay[k], vz = uz + az[k];
+    const bool sl = SOLIDS && !fluid;
+    const real vx = sl ? real(0) : ux + ax[k], vy = sl ? real(0) : uy + ay[k],
+               vz = sl ? real(0) : uz + az[k];
     const real S = om * drho[k] - real(1.5) * rho[k] * ((vx * vx + vy * vy + vz * vz) - ouu);
     const real A = real(4.5) * rho[k], B = real(3) * rho[k];
     const real wS[2] = {real(W1) * S, real(W2) * S};
@@ -478,7 +488,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
       // out-of-range offset, without a branch
       if (SOLIDS)
         buf_store(buf_rsrc(fk + size_t(i) * N, N * uint32_t(sizeof(real))),
-                  ((smask >> i) & 1u) ? n * uint32_t(sizeof(real)) : kOffNone, fluid ? v : real(0));
+                  ((smask >> i) & 1u) ? n * uint32_t(sizeof(real)) : kOffNone, v);
       else if (smask & (1u << i))
         st32(fk + size_t(i) * N, n, v);
       // the link's post-collision value, for the lane that will take the link
