@@ -52,6 +52,26 @@ def test_required_sizes_scale_with_the_box():
     assert sa.adjoint >= (4 + 5) * sa.f
 
 
+def test_work_buffer_holds_the_node_lists_at_their_bound():
+    """A sphere owns only nodes closer than R to its centre, and the unit cubes
+    around them lie inside the ball of radius R + 1: the frontier list needs at
+    most 4/3 pi (R + 1)^3 entries per sphere and the event list twice that
+    (8 bytes an entry), both capped by the node count."""
+    import math
+    shape = (96, 96, 96)
+    N = math.prod(shape)
+    base = required_sizes(Params(*shape, max_particles=0)).work
+    for P, R in ((40, 5.5), (200, 3.0)):
+        w = required_sizes(Params(*shape, max_particles=P, radius=R)).work
+        per = math.ceil(4.0 / 3.0 * math.pi * (R + 1.0) ** 3)
+        need = 8 * (min(N, P * per) + min(N, 2 * P * per))
+        assert w - base >= need, (P, R, w - base, need)
+    # when the bound passes the node count, the node count caps both lists
+    big = required_sizes(Params(24, 24, 24, max_particles=60, radius=5.5)).work
+    small = required_sizes(Params(24, 24, 24, max_particles=0)).work
+    assert big - small < 8 * 3 * 24 ** 3 + 64 * 1024
+
+
 @pytest.mark.parametrize("change,code", [
     (dict(tau=(0.5, 1.0)), B.LB_E_ARG),
     (dict(tau=(1.0, 0.3)), B.LB_E_ARG),
