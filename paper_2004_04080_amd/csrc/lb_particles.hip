@@ -1,11 +1,12 @@
 // lb_particles.hip -- sphere kernels of the gfx950 path (FP64 throughout).
 //
 // Map maintenance uses two owner maps in ping-pong: at step t the "old" map
-// holds M_{t-1} = raster(x(t-1)) and the "new" one still holds
-// raster(x(t-2)); it is cleared around x(t-2) and re-rasterised at x(t).
-// Each sphere is handled by one workgroup sweeping its bounding box, so the
-// per-sphere sums (destroyed/created nodes, frontier Shan-Chen force) are
-// block reductions written without atomics.
+// holds M_{t-1} = raster(x(t-1)) and the "new" one, cleared, is rasterised
+// at x(t). One workgroup per sphere then walks its box and lists the frontier
+// nodes and the node events of the step; the fill and event kernels run over
+// those lists, one thread per entry. Per-sphere sums (destroyed and created
+// nodes, frontier Shan-Chen force) are wave-level sums over runs of lanes of
+// one sphere, added with FP64 atomics.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -118,30 +119,6 @@ __device__ __forceinline__ void stage_push(Stage<CAP>& st, bool put, uint2 v) {
   if (put) st.e[w + int(__popcll(has & ((1ull << lane) - 1ull)))] = v;
 }
 
-// Sum NV doubles over the workgroup; thread 0 gets the result.
-template <int NV>
-__device__ void block_sum(double v[NV]) {
-  __shared__ double sh[NV][PBLOCK / 64];
-  const int lane = __lane_id(), wv = threadIdx.x / 64;
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    double s = v[c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) sh[c][wv] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      double s = 0;
-      for (int w = 0; w < PBLOCK / 64; ++w) s += sh[c][w];
-      v[c] = s;
-    }
-  }
-  __syncthreads();
-}
-
 // walls + empty fluid
 __global__ void k_map_reset(uint16_t* own, uint32_t nx, uint32_t ny, uint32_t nz, int walls) {
   const uint32_t n = blockIdx.x * PBLOCK + threadIdx.x;
@@ -202,14 +179,16 @@ __global__ void __launch_bounds__(PBLOCK) k_raster(PArgs a, int which, int near_
   });
 }
 
-// Fluid-node destruction (Eq. distr) and creation (Eq. creat), one thread per
-// node, from the map of the current populations (own_old) and the new map
-// (own_new). A destroyed node hands its bare momentum sum_k j_k to its new
-// sphere; a created node gets f_eq(rho_bar_k, u_w) in the slots it gathers
-// from, with rho_bar the w-weighted mean over the neighbours fluid in both
-// maps, and the sphere it left loses the momentum sum_k rho_bar_k u_w. Both
-// are summed per sphere into F_d, T_d, F_c, T_c (wave-segmented sums, then
-// FP64 atomics; the accumulators are cleared at the start of the step).
+// Fluid-node destruction (Eq. distr) and creation (Eq. creat) between the map
+// of the current populations (own_old) and the new map (own_new), one thread
+// per entry of the event list. A destroyed node hands its bare momentum
+// sum_k j_k to its new sphere; a created node gets f_eq(rho_bar_k, u_w) in
+// the slots it gathers from, with rho_bar the w-weighted mean over the
+// neighbours fluid in both maps, and the sphere it left loses the momentum
+// sum_k rho_bar_k u_w. Both are summed per sphere into F_d, T_d, F_c, T_c
+// (wave-segmented sums, then FP64 atomics; the accumulators are cleared at
+// the start of the step).
+//
 // One node event: node n destroyed (fluid -> sphere `sphere`) or created
 // (sphere `sphere` -> fluid); its momentum terms go to v (for sphere pid).
 template <typename real, int NC>
@@ -409,17 +388,18 @@ __global__ void __launch_bounds__(PBLOCK) k_sphere_lists(PArgs a, NodeList fl, N
 }
 
 // Virtual densities on the sphere frontier (Eq. soliddens) and the Shan-Chen
-// force those nodes feel (Eq. shanchen2), one thread per node: a solid node
-// of a sphere with at least one fluid neighbour takes the w-weighted mean of
-// the pseudo-potential of those neighbours; with forces on, its force
+// force those nodes feel (Eq. shanchen2): a solid node of a sphere with at
+// least one fluid neighbour takes the w-weighted mean of the pseudo-potential
+// of those neighbours; with forces on, its force
 // F = -G s sum_k psi_k(n) sum_{i: n+c_i fluid} w_i psi_kbar(n+c_i) c_i and the
 // torque about the sphere centre are summed into F_SC, T_SC of its sphere.
 // Wall nodes are left to the wall fill.
 //
-// The frontier nodes come from a list (k_sphere_lists), one thread per entry, so
-// that the waves are full: walking every node of the box instead leaves most
-// lanes of a wave idle, since a wave crossing a sphere holds a handful of its
-// frontier nodes among fluid and interior nodes.
+// The frontier nodes come from a list (k_sphere_lists), one thread per entry,
+// so that the waves are full: walking every node of the box instead leaves
+// most lanes of a wave idle, since a wave crossing a sphere holds a handful
+// of its frontier nodes among fluid and interior nodes.
+//
 // One frontier node n of sphere o with fluid-neighbour mask `mask`: its
 // virtual densities, and with forces on its Shan-Chen force and torque
 // (v, for sphere pid).
@@ -834,10 +814,11 @@ hipError_t launch_clear_accumulators(lb_ctx* c) {
   return hipMemsetAsync(pacc(c), 0, size_t(c->nparticles) * ASTRIDE * sizeof(double), c->stream);
 }
 
-// On stream s: clear the per-step sphere accumulators, move the spheres in
-// the map (clear their nodes of two steps back, claim those at the current
-// centre) and sum the Hertz pair forces through the cell list. Independent
-// of the populations, so it can run beside the density pass.
+// On stream s: clear the per-step sphere accumulators, sum the Hertz and
+// lubrication pair forces through the cell list (flagging spheres that may
+// share nodes), rebuild the new map at the current centres, and list its
+// frontier and the node events of the step. Independent of the populations,
+// so it can run beside the density pass.
 hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   uint16_t* own_new = static_cast<uint16_t*>(c->B.owner[1 - c->own_old]);
   const uint16_t* own_old = static_cast<const uint16_t*>(c->B.owner[c->own_old]);
