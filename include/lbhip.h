@@ -200,14 +200,19 @@ int lb_add_particles(struct lb_ctx* ctx, int32_t n, const double* x, const doubl
                      const double* w, const double* q);
 
 /* Advance nsteps time steps (Sec. 3.1, eight-step sequence). Asynchronous on
- * the context's stream. A sphere faster than 1/2 node per step is flagged
- * and reported by the next synchronising call. With checkpoint_every > 0 the
- * steps are recorded for lb_backward (LB_E_CAPACITY beyond max_record_steps).
+ * the context's stream. With moving spheres the map update of each step runs
+ * on a second stream that the context creates on first use (default
+ * priority); it waits for the context's stream and is joined back into it
+ * before the step goes on, so callers see one stream. A sphere faster than
+ * 1/2 node per step is flagged and reported by the next synchronising call.
+ * With checkpoint_every > 0 the steps are recorded for lb_backward
+ * (LB_E_CAPACITY beyond max_record_steps).
  * Errors: LB_E_ARG, LB_E_HIP, LB_E_CAPACITY. */
 int lb_step(struct lb_ctx* ctx, int32_t nsteps);
 
 /* FP64 observables of the current state. Synchronises.
- * Errors: LB_E_PARTICLE_SPEED / LB_E_NONFINITE when flagged (out is still filled). */
+ * Errors: LB_E_PARTICLE_SPEED / LB_E_NONFINITE / LB_E_CAPACITY (node-list
+ * overflow) when flagged (out is still filled). */
 int lb_observables(struct lb_ctx* ctx, lb_obs* out);
 
 /* Moments of the current state on fluid nodes (0 on solid nodes), host FP64:
