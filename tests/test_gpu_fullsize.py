@@ -1,6 +1,7 @@
-"""One-step parity of the FP32 path at the full bench size: a 512^3 box with
-two fluids and 32,000 moving spheres of radius 5.5, built with the same
-parameters that bench.py times.
+"""One-step parity of the FP32 path at full size: the bench box (512^3, two
+fluids, 32,000 moving spheres of radius 5.5) and the confined box
+(512x512x256 between moving walls, 20,000 spheres of radius 4), each built
+with the parameters that bench.py uses for it.
 
 The oracle cannot step the whole box, so it steps windows of it. After a few
 steps on the GPU, the state (FP32 populations read out as FP64, the map and
@@ -32,8 +33,8 @@ TOL32 = 1e-5
 TOL32_U = 5e-5  # derivation in tests/test_gpu_parity.py
 
 
-def _window_index(origin, shape):
-    ax = [(origin[d] + np.arange(W)) % shape[d] for d in range(3)]
+def _window_index(origin, shape, win):
+    ax = [(origin[d] + np.arange(win[d])) % shape[d] for d in range(3)]
     z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
     return (x + shape[0] * (y + shape[1] * z)).reshape(-1).astype(np.int64)
 
@@ -42,18 +43,21 @@ def _eps(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def test_full_size_one_step_parity_on_windows():
+def _window_parity(name, origins):
+    """Step the bench state of workload `name` on the GPU, then one step of
+    each window in the oracle; compare the window interiors. With walls a
+    window spans the whole z height with the real walls, and only its x and y
+    faces are periodic wraps (and excluded from the comparison)."""
     import bench
     from paper_2004_04080_amd import Lattice
-    w = synth.workload("T")
+    w = synth.workload(name)
     shape = (w.nx, w.ny, w.nz)
-    print("[fullsize] building the 512^3 state", flush=True)
+    win = (W, W, w.nz if w.walls else W)
+    print(f"[fullsize] building the {shape} state of {name}", flush=True)
     lat = Lattice(bench.params_for(w, "fp32"), w.densities())
     lat.add_particles(w.centres())
     lat.step(3)
-    rng = np.random.default_rng(5)
-    origins = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(4)]
-    idx = [_window_index(o, shape) for o in origins]
+    idx = [_window_index(o, shape, win) for o in origins]
     f = lat.populations()
     f0 = [f[:, :, i] for i in idx]
     del f
@@ -77,16 +81,24 @@ def test_full_size_one_step_parity_on_windows():
     perm = perm_gpu_for_oracle()
     L = np.array(shape, dtype=float)
     R = w.radius
-    half = (W - 1) / 2.0
+    half = (np.array(win, dtype=float) - 1) / 2.0
+    wrapped = np.array([True, True, not w.walls])   # axes where the window is a periodic cut
     REC = O.REC
-    inner = np.zeros((W, W, W), dtype=bool)
-    inner[MARGIN:W - MARGIN, MARGIN:W - MARGIN, MARGIN:W - MARGIN] = True
+    inner = np.ones(win[::-1], dtype=bool)           # [z][y][x]
+    for a in range(3):
+        if wrapped[a]:
+            sl = [slice(None)] * 3
+            keep = np.zeros(win[a], dtype=bool)
+            keep[MARGIN:win[a] - MARGIN] = True
+            shape_a = [1, 1, 1]
+            shape_a[2 - a] = win[a]
+            inner &= keep.reshape(shape_a)
     inner = inner.reshape(-1)
     nspheres_checked = 0
     for k, org in enumerate(origins):
         # spheres that can touch the window, in window coordinates, global order kept
         d = rec0[:, REC["x"]:REC["x"] + 3] - (np.array(org, dtype=float) + half)
-        d -= L * np.round(d / L)
+        d -= np.where(wrapped, L * np.round(d / L), 0.0)
         sel = np.flatnonzero(np.all(np.abs(d) < half + R + 1.0, axis=1))
         xw = d[sel] + half
         local = np.zeros(len(rec0) + 1, dtype=np.int32)
@@ -95,9 +107,10 @@ def test_full_size_one_step_parity_on_windows():
         def to_local(o):
             return np.where(o > 0, local[np.maximum(o, 0)], o)
 
-        po = O.Params(W, W, W, ncomp=2, tau=w.tau, G=w.G, sc_norm=1.0, g=w.g, radius=R,
-                      particle_density=w.particle_density, hertz_K=0.0)
-        o = O.Oracle(po, np.ones((2, W ** 3)))
+        po = O.Params(*win, ncomp=2, tau=w.tau, G=w.G, sc_norm=1.0, g=w.g, radius=R,
+                      particle_density=w.particle_density, hertz_K=0.0, walls=w.walls,
+                      wall_u_lo=w.wall_u_lo, wall_u_hi=w.wall_u_hi)
+        o = O.Oracle(po, np.ones((2, int(np.prod(win)))))
         o.add_particles(xw)
         r = o.particles()
         for key, n in (("v", 3), ("w", 3), ("q", 4), ("Fprev", 3), ("Tprev", 3)):
@@ -120,14 +133,15 @@ def test_full_size_one_step_parity_on_windows():
              "rho0": _eps(rg[0], ro[0]), "rho1": _eps(rg[1], ro[1]),
              "phi": _eps(rg[0] - rg[1], ro[0] - ro[1]),
              "u": _eps(u1[k][m], o.u()[m])}
-        print(f"[fullsize] window {org}: {m.sum()} fluid nodes, "
+        print(f"[fullsize] {name} window {org}: {m.sum()} fluid nodes, "
               + " ".join(f"{a} {b:.1e}" for a, b in e.items()), flush=True)
         for key in ("f", "rho0", "rho1", "phi"):
             assert e[key] <= TOL32, (org, key, e[key])
         assert e["u"] <= TOL32_U, (org, e["u"])
 
         # spheres whose links and events all fall in the compared interior
-        lo, hi = MARGIN + R + 2.0, W - 1 - MARGIN - R - 2.0
+        lo = np.where(wrapped, MARGIN + R + 2.0, -np.inf)
+        hi = np.where(wrapped, np.array(win) - 1 - MARGIN - R - 2.0, np.inf)
         whole = np.flatnonzero(np.all((xw >= lo) & (xw <= hi), axis=1))
         ro_p = o.particles()
         for j in whole:
@@ -138,5 +152,20 @@ def test_full_size_one_step_parity_on_windows():
                 err = np.abs(gp[REC[key]:REC[key] + 3] - op[REC[key]:REC[key] + 3]).max() / scale
                 assert err < TOL32, (org, int(sel[j]), key, err)
         nspheres_checked += len(whole)
-    print(f"[fullsize] spheres compared: {nspheres_checked}", flush=True)
+    print(f"[fullsize] {name}: spheres compared: {nspheres_checked}", flush=True)
     assert nspheres_checked > 0
+
+
+def test_full_size_one_step_parity_on_windows():
+    """The bench box: 512^3, 32,000 moving spheres of radius 5.5."""
+    rng = np.random.default_rng(5)
+    origins = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(4)]
+    _window_parity("T", origins)
+
+
+def test_confined_box_one_step_parity_on_windows():
+    """The confined case: 512x512x256 between walls moving at -+0.01 in x,
+    20,000 spheres of radius 4. Each window spans the full height."""
+    rng = np.random.default_rng(6)
+    origins = [(int(rng.integers(0, 512)), int(rng.integers(0, 512)), 0) for _ in range(3)]
+    _window_parity("C4", origins)
