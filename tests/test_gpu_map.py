@@ -93,3 +93,56 @@ def test_restored_state_replaces_the_cached_frontier_of_fixed_spheres():
     assert err <= 1e-14
     a.close()
     b.close()
+
+
+def test_sphere_wider_than_the_box_is_listed_once():
+    """A sphere of radius 5.2 in a 12 x 13 x 14 box: its bounding box (up to
+    13 nodes a side) is wider than the 12-node axis, so its walk sees a node
+    twice unless it walks one period only. Moving, in FP64, against the
+    oracle."""
+    shape = (12, 13, 14)
+    w = synth.Workload("tiny", *shape, seed=synth.BASE_SEED + 63)
+    x = np.array([[5.7, 6.1, 7.3]])
+    v = np.array([[0.03, -0.02, 0.01]])
+    om = np.array([[0.0, 0.01, 0.02]])
+    o, lat = make_pair(shape, w.densities(), x=x, v=v, w=om, G=0.65, radius=5.2,
+                       particle_density=2.0, zeta=(0.1, -0.1))
+    done = 0
+    for h in (1, 10, 30):
+        assert o.step(h - done) == 0
+        lat.step(h - done)
+        done = h
+        e = compare(o, lat)
+        print(f"[map] tiny box t={h}", {k: (f"{v:.1e}" if isinstance(v, float) else v)
+                                        for k, v in e.items()}, flush=True)
+        assert e.pop("owner_equal")
+        e.pop("df")
+        for k, val in e.items():
+            assert val <= 1e-11, (h, k, val)
+        ep = compare_particles(o, lat)
+        assert ep["x"] < 1e-11 and ep["v"] < 1e-11
+        for k in ("Fliq", "Tliq", "Fd", "Td", "Fc", "Tc", "FSC", "TSC"):
+            assert ep[k] < 1e-12, (h, k, ep[k])
+    assert (o.owner() == 0).sum() > 0 and (o.owner() == 1).sum() > 0
+
+
+def test_capacity_without_spheres_steps_like_no_spheres():
+    """A context sized for spheres but given none steps as one without sphere
+    capacity. It runs the collide that reads the owner map (all fluid here),
+    a separate instance of the same arithmetic, so rounding may differ in the
+    last place; the fields must agree to the FP32 bound."""
+    from paper_2004_04080_amd import Lattice, Params
+    shape = (24, 20, 16)
+    w = synth.Workload("nosph", *shape, seed=synth.BASE_SEED + 64)
+    a = Lattice(Params(*shape, precision="fp32", G=0.65), w.densities())
+    b = Lattice(Params(*shape, precision="fp32", G=0.65, max_particles=8, radius=3.0),
+                w.densities())
+    a.step(25)
+    b.step(25)
+    fa, fb = a.populations(), b.populations()
+    err = float(np.abs(fb - fa).max() / np.abs(fa).max())
+    print(f"[map] capacity without spheres: {err:.1e}", flush=True)
+    assert err <= 1e-6
+    assert b.num_particles() == 0 and b.observables().flags == 0
+    a.close()
+    b.close()
