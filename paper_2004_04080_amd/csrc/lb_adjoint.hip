@@ -544,11 +544,11 @@ int backward(lb_ctx* c, const double* seedA, const double* seedB, double* dA0, d
     return LB_E_HIP;
   };
   hipError_t e = hipSuccess;
-  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemsetAsync(mu[b], 0, mubytes, c->stream);
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = launch_zero(mu[b], mubytes, c->stream);
   if (e == hipSuccess)
-    e = hipMemsetAsync(aptr(c, c->al.lam_a), 0, size_t(g.ncomp) * 3 * N * sizeof(double), c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(lam_psi, 0, size_t(g.ncomp) * N * sizeof(double), c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(accum, 0, 4 * sizeof(double), c->stream);
+    e = launch_zero(aptr(c, c->al.lam_a), size_t(g.ncomp) * 3 * N * sizeof(double), c->stream);
+  if (e == hipSuccess) e = launch_zero(lam_psi, size_t(g.ncomp) * N * sizeof(double), c->stream);
+  if (e == hipSuccess) e = launch_zero(accum, 4 * sizeof(double), c->stream);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_adj_fill_weights, dim3(ablocks(N)), dim3(ABLOCK), 0, c->stream, own,
                        g.nx, g.ny, g.nz, reinterpret_cast<double*>(aptr(c, c->al.winv)));

@@ -292,9 +292,9 @@ int lb_domain_size(lb_ctx* c, void* work, size_t work_bytes, double* L, double* 
   hipLaunchKernelGGL(k_phi_mean, dim3(1), blk, 0, s, partial, d.nblocks);
   hipLaunchKernelGGL(k_phi_center, grid, blk, 0, s, x, own, g.N, partial);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemsetAsync(bins, 0, size_t(d.nshell) * sizeof(double), s);
+  if (e == hipSuccess) e = launch_zero(bins, size_t(d.nshell) * sizeof(double), s);
   if (e == hipSuccess)
-    e = hipMemsetAsync(counts, 0, size_t(d.nshell) * sizeof(unsigned long long), s);
+    e = launch_zero(counts, size_t(d.nshell) * sizeof(unsigned long long), s);
   if (e != hipSuccess) {
     c->err = std::string("lb_domain_size: ") + hipGetErrorString(e);
     return LB_E_HIP;

@@ -123,6 +123,8 @@ hipError_t launch_owner_to_int(lb_ctx* c, const uint16_t* owner, uint32_t first,
 // particles
 hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner);   // walls + all spheres at x
 hipError_t launch_map_update(lb_ctx* c, hipStream_t s);  // clear, unraster, raster, pairs
+// zero bytes at p on stream s with a fill kernel (graph-capture safe)
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_events(lb_ctx* c);                     // node creation / destruction
 // frontier list of the sphere map `owner`, whose spheres sit around the
 // centres at record offset `which`, on stream s; with owner_old set, also

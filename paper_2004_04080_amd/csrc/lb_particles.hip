@@ -811,7 +811,7 @@ hipError_t launch_raster_full(lb_ctx* c, uint16_t* owner) {
 }
 
 hipError_t launch_clear_accumulators(lb_ctx* c) {
-  return hipMemsetAsync(pacc(c), 0, size_t(c->nparticles) * ASTRIDE * sizeof(double), c->stream);
+  return launch_zero(pacc(c), size_t(c->nparticles) * ASTRIDE * sizeof(double), c->stream);
 }
 
 // On stream s: clear the per-step sphere accumulators, sum the Hertz and
@@ -824,7 +824,7 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   const uint16_t* own_old = static_cast<const uint16_t*>(c->B.owner[c->own_old]);
   const PArgs a = pargs(c, own_new, own_old);
   const dim3 gp(c->nparticles), bp(PBLOCK);
-  hipError_t e0 = hipMemsetAsync(pacc(c), 0, size_t(c->nparticles) * ASTRIDE * sizeof(double), s);
+  hipError_t e0 = launch_zero(pacc(c), size_t(c->nparticles) * ASTRIDE * sizeof(double), s);
   if (e0 != hipSuccess) return e0;
   // Hertz pairs through the cell list
   CellArgs ca;
@@ -851,7 +851,7 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   ca.lub_mu = c->P.lub_mu;
   ca.lub_hn = c->P.lub_hn;
   ca.lub_hcap = c->P.lub_hcap;
-  hipError_t e = hipMemsetAsync(ca.count, 0, size_t(ncell) * sizeof(int32_t), s);
+  hipError_t e = launch_zero(ca.count, size_t(ncell) * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
   const dim3 gt((c->nparticles + PBLOCK - 1) / PBLOCK);
   hipLaunchKernelGGL(k_cell_count, gt, bp, 0, s, ca);
@@ -860,7 +860,7 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_sort, dim3((ncell + PBLOCK - 1) / PBLOCK), bp, 0, s, ca, ncell);
   hipLaunchKernelGGL(k_pairs, gt, bp, 0, s, ca);
   // the new map: cleared, walls, spheres at the current centres
-  e = hipMemsetAsync(own_new, 0, size_t(c->geo.N) * sizeof(uint16_t), s);
+  e = launch_zero(own_new, size_t(c->geo.N) * sizeof(uint16_t), s);
   if (e != hipSuccess) return e;
   if (c->P.walls) {
     const uint32_t plane = c->geo.nx * c->geo.ny;
@@ -895,8 +895,8 @@ hipError_t launch_sphere_lists(lb_ctx* c, const uint16_t* owner, const uint16_t*
                                int which, hipStream_t s) {
   const NodeList fl = frontier_list(c);
   NodeList ev = event_list(c);
-  hipError_t e = hipMemsetAsync(fl.count, 0, sizeof(int32_t), s);
-  if (e == hipSuccess && owner_old) e = hipMemsetAsync(ev.count, 0, sizeof(int32_t), s);
+  hipError_t e = launch_zero(fl.count, sizeof(int32_t), s);
+  if (e == hipSuccess && owner_old) e = launch_zero(ev.count, sizeof(int32_t), s);
   if (e != hipSuccess) return e;
   if (!owner_old) ev.list = nullptr;
   if (c->nparticles > 0)
