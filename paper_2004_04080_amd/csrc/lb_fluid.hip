@@ -814,31 +814,6 @@ static void density_t(lb_ctx* c, const void* f) {
                        g.nx, g.ny, g.nz, bpx);
 }
 
-// Zero `bytes` bytes at p: 16-byte stores for the aligned body, single bytes
-// for the edges. The step clears its buffers with this kernel rather than a
-// memset: a caller may capture steps into a graph, and memset nodes have
-// given wrong results on graph replays on this hardware.
-__global__ void __launch_bounds__(BLOCK) k_zero(unsigned char* __restrict__ p, size_t bytes) {
-  const size_t head = (16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u;
-  const size_t h = head < bytes ? head : bytes;
-  const size_t body = (bytes - h) / 16;
-  const size_t tid = size_t(blockIdx.x) * BLOCK + threadIdx.x;
-  const size_t nth = size_t(gridDim.x) * BLOCK;
-  uint4* q = reinterpret_cast<uint4*>(p + h);
-  for (size_t i = tid; i < body; i += nth) q[i] = make_uint4(0u, 0u, 0u, 0u);
-  const size_t done = h + body * 16;
-  if (tid < h) p[tid] = 0;
-  if (tid < bytes - done) p[done + tid] = 0;
-}
-
-hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
-  if (bytes == 0) return hipSuccess;
-  const size_t blocks = std::min<size_t>((bytes / 16 + BLOCK - 1) / BLOCK, 4096);
-  hipLaunchKernelGGL(k_zero, dim3(uint32_t(std::max<size_t>(blocks, 1))), dim3(BLOCK), 0, s,
-                     static_cast<unsigned char*>(p), bytes);
-  return hipGetLastError();
-}
-
 hipError_t launch_density(lb_ctx* c, const void* f) {
   if (fp64(c)) density_t<double>(c, f);
   else density_t<float>(c, f);

@@ -9,6 +9,7 @@
 // one sphere, added with FP64 atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "lb_device.hpp"
@@ -764,6 +765,31 @@ __global__ void k_integrate(double* ps, const double* acc, int np, double mass, 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Zero `bytes` bytes at p: 16-byte stores for the aligned body, single bytes
+// for the edges. The step clears its buffers with this kernel rather than a
+// memset: a caller may capture steps into a graph, and memset nodes have
+// given wrong results on graph replays on this hardware.
+__global__ void __launch_bounds__(PBLOCK) k_zero(unsigned char* __restrict__ p, size_t bytes) {
+  const size_t head = (16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u;
+  const size_t h = head < bytes ? head : bytes;
+  const size_t body = (bytes - h) / 16;
+  const size_t tid = size_t(blockIdx.x) * PBLOCK + threadIdx.x;
+  const size_t nth = size_t(gridDim.x) * PBLOCK;
+  uint4* q = reinterpret_cast<uint4*>(p + h);
+  for (size_t i = tid; i < body; i += nth) q[i] = make_uint4(0u, 0u, 0u, 0u);
+  const size_t done = h + body * 16;
+  if (tid < h) p[tid] = 0;
+  if (tid < bytes - done) p[done + tid] = 0;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((bytes / 16 + PBLOCK - 1) / PBLOCK, 4096);
+  hipLaunchKernelGGL(k_zero, dim3(uint32_t(std::max<size_t>(blocks, 1))), dim3(PBLOCK), 0, s,
+                     static_cast<unsigned char*>(p), bytes);
+  return hipGetLastError();
+}
+
 static PArgs pargs(lb_ctx* c, uint16_t* own_new, const uint16_t* own_old) {
   PArgs a;
   a.own_new = own_new;
