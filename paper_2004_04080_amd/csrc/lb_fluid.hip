@@ -255,8 +255,10 @@ __device__ __forceinline__ void link_one(const CollideArgs& a, int i, uint16_t o
 
 // Links of one wave, gathered in LDS so that every lane takes one link at a
 // time instead of each lane walking its own (a wave would otherwise iterate
-// as often as its busiest lane has links). Entries beyond the capacity are
-// left to their lanes (see k_collide).
+// as often as its busiest lane has links). The queues of a workgroup's waves
+// are then processed as one list, in 64-entry chunks dealt to the waves, so
+// the links fill as few waves as they need. Entries beyond a wave's capacity
+// are left to their lanes (see k_collide).
 constexpr int QW = 256;
 // With 4-byte values every lane keeps all its post-collision values, indexed
 // by (direction, lane), which costs one LDS store per value and no index
@@ -522,22 +524,35 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
   lq.u[0][lane] = ux;
   lq.u[1][lane] = uy;
   lq.u[2][lane] = uz;
-  // the wave's own LDS writes, in order, before any lane reads them
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int e = lane; e < qtotal; e += 64) {
-    const uint32_t m = lq.meta[e];
+  // The block's queues form one list: wave w takes its 64-entry chunks w,
+  // w + W, ... (W waves per block), so a block's links fill as few waves as
+  // they need and the other waves skip the link phase.
+  constexpr int WPB = BLOCK / 64;
+  __shared__ int qtot[WPB];
+  if (lane == 0) qtot[threadIdx.x / 64] = qtotal;
+  __syncthreads();
+  int pre[WPB + 1];
+  pre[0] = 0;
+#pragma unroll
+  for (int w = 0; w < WPB; ++w) pre[w + 1] = pre[w] + qtot[w];
+  const int QB = pre[WPB];
+  for (int E = int(threadIdx.x); E < QB; E += BLOCK) {
+    int ws = 0;
+#pragma unroll
+    for (int w = 1; w < WPB; ++w) ws += E >= pre[w] ? 1 : 0;
+    const int e = E - pre[ws];
+    const LinkQueue<real, NC>& q = lqs[ws];
+    const uint32_t m = q.meta[e];
     const int src = int(m & 63u), i = int((m >> 6) & 31u);
     const uint16_t o = uint16_t(m >> 11);
     real fs[NC], rk[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      fs[k] = lq.fs[k][kDenseLinks<real> ? i * 64 + src : e];
-      rk[k] = lq.rho[k][src];
+      fs[k] = q.fs[k][kDenseLinks<real> ? i * 64 + src : e];
+      rk[k] = q.rho[k][src];
     }
-    const real us[3] = {lq.u[0][src], lq.u[1][src], lq.u[2][src]};
-    link_one<real, NC>(a, i, o, lq.x[src], lq.y[src], lq.z[src], fs, rk, us, pid, lv);
+    const real us[3] = {q.u[0][src], q.u[1][src], q.u[2][src]};
+    link_one<real, NC>(a, i, o, q.x[src], q.y[src], q.z[src], fs, rk, us, pid, lv);
   }
   if (!queued) {
     // past the wave's capacity: this lane walks its own links, reading back
