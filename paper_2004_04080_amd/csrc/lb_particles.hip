@@ -555,10 +555,14 @@ __global__ void k_cell_count(CellArgs a) {
 }
 
 // exclusive scan of count into start (single workgroup), then clear count;
-// tiles of 8 consecutive cells per thread keep the serial rounds few
-__global__ void __launch_bounds__(1024) k_cell_scan(int32_t* count, int32_t* start, int ncell) {
-  constexpr int PER = 8, TILE = 1024 * PER;
-  __shared__ int32_t wsum[16];
+// tiles of 32 consecutive cells per thread keep the serial rounds few. The
+// workgroup is one wave per SIMD, so that it finds a compute unit at once
+// while the density pass fills the chip.
+constexpr int kScanThreads = 256;
+__global__ void __launch_bounds__(kScanThreads) k_cell_scan(int32_t* count, int32_t* start,
+                                                            int ncell) {
+  constexpr int PER = 32, TILE = kScanThreads * PER;
+  __shared__ int32_t wsum[kScanThreads / 64];
   __shared__ int32_t carry;
   const int lane = __lane_id(), wv = int(threadIdx.x) / 64;
   if (threadIdx.x == 0) carry = 0;
@@ -591,7 +595,7 @@ __global__ void __launch_bounds__(1024) k_cell_scan(int32_t* count, int32_t* sta
         run += v[j];
       }
     __syncthreads();
-    if (threadIdx.x == 1023) carry = run;
+    if (threadIdx.x == kScanThreads - 1) carry = run;
     __syncthreads();
   }
   if (threadIdx.x == 0) start[ncell] = carry;
@@ -881,7 +885,7 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   if (e != hipSuccess) return e;
   const dim3 gt((c->nparticles + PBLOCK - 1) / PBLOCK);
   hipLaunchKernelGGL(k_cell_count, gt, bp, 0, s, ca);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ca.count, ca.start, ncell);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanThreads), 0, s, ca.count, ca.start, ncell);
   hipLaunchKernelGGL(k_cell_fill, gt, bp, 0, s, ca);
   hipLaunchKernelGGL(k_cell_sort, dim3((ncell + PBLOCK - 1) / PBLOCK), bp, 0, s, ca, ncell);
   hipLaunchKernelGGL(k_pairs, gt, bp, 0, s, ca);
