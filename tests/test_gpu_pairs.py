@@ -1,0 +1,76 @@
+"""Hertz pair forces through a cell list of many cells, against the oracle.
+
+Spheres of radius 1.5 give cells of side d0 = 2R + 1 = 4, so the 160x160x64
+box holds 40 x 40 x 16 = 25,600 cells: the cell-start scan then runs over
+several tiles of 8,192 cells and carries its running sum from tile to tile.
+600 pairs of spheres, 3.6 apart (inside the contact range d0 = 4, outside the
+cap 2R), are spread over the whole box, so non-empty cells lie in every tile.
+FP64, moving spheres; the pair forces, the other sphere forces, the sphere
+state, the map and the fields must agree with the oracle at the bounds of the
+other moving-sphere tests.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import compare, compare_particles, make_pair, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+SHAPE = (160, 160, 64)
+R = 1.5
+GAP = 3.6
+
+
+def _pairs(seed, npairs=600, excl=6.5):
+    rng = np.random.default_rng(seed)
+    L = np.array(SHAPE, dtype=float)
+    mids = []
+    while len(mids) < npairs:
+        c = rng.uniform(0, 1, 3) * L
+        if mids:
+            d = np.array(mids) - c
+            d -= L * np.round(d / L)
+            if (d ** 2).sum(1).min() < excl * excl:
+                continue
+        mids.append(c)
+    x = []
+    for c in mids:
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        x += [(c - 0.5 * GAP * e) % L, (c + 0.5 * GAP * e) % L]
+    return np.array(x)
+
+
+def test_pair_forces_over_many_cells():
+    x = _pairs(synth.BASE_SEED + 81)
+    side = max(1.0, 2 * R + 1, 2 * R + 0.5)
+    ncell = int(np.prod([int(n // side) for n in SHAPE]))
+    print(f"[pairs] {len(x)} spheres, {ncell} cells of side {side}", flush=True)
+    assert ncell > 3 * 8192
+    w = synth.Workload("pairs", *SHAPE, seed=synth.BASE_SEED + 82)
+    o, lat = make_pair(SHAPE, w.densities(), x=x, G=0.65, radius=R, particle_density=2.0,
+                       hertz_K=0.01, zeta=(0.05, -0.05))
+    done = 0
+    for h in (1, 2):
+        assert o.step(h - done) == 0
+        lat.step(h - done)
+        done = h
+        e = compare(o, lat)
+        ep = compare_particles(o, lat)
+        print(f"[pairs] t={h}", {k: (f"{v:.1e}" if isinstance(v, float) else v)
+                                 for k, v in e.items()},
+              {k: f"{v:.1e}" for k, v in ep.items()}, flush=True)
+        assert e.pop("owner_equal"), f"maps differ at t={h}"
+        e.pop("df")
+        for k, val in e.items():
+            assert val <= 1e-11, (h, k, val)
+        assert ep["x"] < 1e-11 and ep["v"] < 1e-11 and ep["w"] < 1e-11
+        for k in ("FH", "Fliq", "Tliq", "FSC", "TSC", "Fd", "Td", "Fc", "Tc"):
+            assert ep[k] < 1e-11, (h, k, ep[k])
+    # every pair is in contact: the Hertz force acts on every sphere
+    fh = np.linalg.norm(o.particles()[:, O.REC["FH"]:O.REC["FH"] + 3], axis=1)
+    assert (fh > 0).all(), int((fh == 0).sum())
+    assert lat.observables().flags == 0
+    lat.close()
