@@ -16,8 +16,9 @@ namespace lbh {
 constexpr int BLOCK = 256;
 
 static inline uint32_t nblocks(uint64_t n) { return uint32_t((n + BLOCK - 1) / BLOCK); }
-// target band width of the collide sweep, in workgroups per z-plane
-constexpr uint32_t kBandTarget = 64;
+// target band width of the collide sweep, in workgroups per z-plane (16
+// workgroups: 4,096 nodes, 8 rows of 512)
+constexpr uint32_t kBandTarget = 16;
 
 // ---------------------------------------------------------------------------
 // Initial populations f_i = f_eq(rho0(n), u0(n)) (Eq. LEQ), written in pull form.
@@ -876,8 +877,9 @@ hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t
   for (int d = 0; d < 3; ++d) a.invL[d] = 1.0 / a.L[d];
   a.nblk = nblocks(g.N);
   a.blocks_per_xcd = (a.nblk + 7) / 8;
-  // bands of about 32 workgroups (8192 nodes) per z-plane, when whole
-  // workgroups tile a z-plane; otherwise plain plane order
+  // bands of at most kBandTarget workgroups per z-plane (the largest width
+  // that divides the plane), when whole workgroups tile a z-plane; otherwise
+  // plain plane order
   a.band_w = 0;
   a.plane_w = 0;
   if ((uint64_t(g.nx) * g.ny) % BLOCK == 0) {
