@@ -966,7 +966,7 @@ hipError_t launch_fill_particles(lb_ctx* c, const uint16_t* owner, bool forces, 
   const NodeList fl = frontier_list(c);
   if (fl.cap == 0) return hipSuccess;
   // enough waves to cover the list in a few passes
-  const dim3 grid(uint32_t(std::min<size_t>((c->wl.fcap + PBLOCK - 1) / PBLOCK, 8192)));
+  const dim3 grid(uint32_t(std::min<size_t>((c->wl.fcap + PBLOCK - 1) / PBLOCK, 32768)));
   const bool two = c->geo.ncomp == 2, janus = c->P.janus != 0;
   const hipStream_t s = c->stream;
   if (c->geo.prec == LB_FP64) {
