@@ -22,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBO_LIB", os.path.join(HERE, "liblbo.so"))
 
 PREC = 50   # doubles per particle record
-NOBS = 32   # observables
+NOBS = 36   # observables
 
 
 class _Params(C.Structure):

@@ -1001,6 +1001,34 @@ void lbo_observables(const void* s, double* out) {
   out[14] = ke.get();
   out[15] = kr.get();
   for (int r = 0; r < 16; ++r) out[16 + r] = S->ledger[r];
+  // Physical fluid momentum (Sec. 2.3, the velocity that follows Eq. lbsbgk
+  // with the exact-difference forcing): sum_k j_k + F_k / 2 on every fluid
+  // node, with the force density F_k of Eq. shanchen (pseudo-potential of the
+  // current map, virtual densities on frontier solids) plus rho_k g.
+  std::vector<double> rt;
+  S->fill(S->own, rho, rt);
+  NSum<double> ph[3];
+  for (int64_t n = 0; n < N; ++n) {
+    if (S->own[n] != 0) continue;
+    for (int k = 0; k < S->K; ++k) {
+      double s[3] = {0.0, 0.0, 0.0};
+      if (S->K == 2)
+        for (int i = 1; i < Q; ++i) {
+          const double r = rt[int64_t(1 - k) * N + S->nb[n * Q + i]] * WT[i];
+          for (int a = 0; a < 3; ++a) s[a] += r * CV[i][a];
+        }
+      const double rk = rho[int64_t(k) * N + n];
+      for (int a = 0; a < 3; ++a) {
+        ph[a].add(j[(int64_t(k) * N + n) * 3 + a]);
+        ph[a].add(0.5 * (-(S->G * S->P.sc_norm) * rk * s[a] + rk * S->g[a]));
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) out[32 + a] = ph[a].get();
+  // sum over the spheres of sum over links of |F_link| of the last step
+  NSum<double> fl;
+  for (auto& pp : S->parts) fl.add(pp.last[27]);
+  out[35] = fl.get();
 }
 
 void lbo_test_rotate(double* q, const double* w, int32_t nsteps) {

@@ -86,7 +86,7 @@ typedef struct lbo_params {
  * 49 1 when Fliq_prev/Tliq_prev hold a previous half-step value, else 0 */
 
 /* observables, lbo_observables() */
-#define LBO_NOBS 32
+#define LBO_NOBS 36
 /*  0 mass A   1 mass B   2..4 bare fluid momentum sum_k j_k
  *  5 rho min A  6 rho min B  7 rho max A  8 rho max B  9 max |u|
  * 10 fluid node count  11..13 particle momentum  14 particle KE (transl.)
@@ -96,7 +96,10 @@ typedef struct lbo_params {
  * 20,21 mass change from the moving-link corrections (A,B)
  * 22..24 body force sum_n sum_k rho_k g on the fluid nodes after the map update
  * 25..27 Shan-Chen force summed over fluid nodes
- * 28..30 link force sum_links F_link over wall links   31 step counter */
+ * 28..30 link force sum_links F_link over wall links   31 step counter
+ * 32..34 physical fluid momentum sum_fluid sum_k (j_k + F_k / 2), F_k the
+ *        Shan-Chen plus body force density of the current state
+ * 35     sum over spheres and links of |F_link| of the last step */
 
 void*   lbo_create(const lbo_params* p, const double* rho0 /* [ncomp][N] */,
                    const double* u0 /* [N][3] or NULL */);

@@ -130,6 +130,25 @@ def test_shan_chen_conserves_global_momentum():
         assert np.abs(ob[25:28]).max() / M < 1e-15
 
 
+def test_physical_momentum_under_a_body_force_closed_form():
+    """With a uniform acceleration g in a periodic box every step adds M g to
+    the bare momentum (the Shan-Chen forces sum to zero), so from rest
+    P_bare(t) = t M g, and the physical momentum (bare plus half the force
+    density, Sec. 2.3 after Eq. lbsbgk) is P_phys(t) = (t + 1/2) M g."""
+    w = synth.Workload("pm", 10, 9, 8, seed=21)
+    g = np.array([2e-5, -1e-5, 3e-6])
+    p = O.Params(10, 9, 8, ncomp=2, G=0.65, sc_norm=1.0, g=tuple(g))
+    o = O.Oracle(p, w.densities())
+    ob = o.observables()
+    M = ob[0] + ob[1]
+    for t in range(0, 31, 10):
+        if t:
+            o.step(10)
+            ob = o.observables()
+        assert np.abs(ob[2:5] - t * M * g).max() < 1e-14 * M * np.abs(g).max() * (t + 1)
+        assert np.abs(ob[32:35] - (t + 0.5) * M * g).max() < 1e-14 * M * np.abs(g).max() * (t + 1)
+
+
 def _growth_matrix(k, omega, Gs, rho0=1.0):
     """Linearised composition dynamics of one Fourier mode exp(i k z) about a
     uniform 50/50 mixture at rest, written from the scheme's definition:

@@ -131,6 +131,33 @@ def test_momentum_and_mass_ledgers_with_moving_spheres(walls):
     assert events > 0
 
 
+@pytest.mark.parametrize("walls", [False, True])
+def test_physical_momentum_matches_the_force_of_the_next_step(walls):
+    """Physical momentum = bare momentum + half the force density summed over
+    the fluid (Sec. 2.3 after Eq. lbsbgk). With fixed spheres the map does not
+    change, so the force of the current state is the force the next step
+    applies, which the momentum ledger above accounts for exactly: Shan-Chen
+    over the fluid nodes (with the virtual densities of the frontier) plus
+    rho g."""
+    L = (18, 16, 20)
+    w = synth.Workload("phys", *L, nparticles=4, radius=3.0, seed=91, walls=walls)
+    p = O.Params(*L, ncomp=2, G=0.65, sc_norm=1.0, g=(1e-4, -5e-5, 2e-5), radius=3.0,
+                 particles_fixed=True, walls=walls, zeta=(0.05, -0.05))
+    o = O.Oracle(p, w.densities())
+    o.add_particles(w.centres())
+    assert o.step(3) == 0
+    for _ in range(3):
+        ob0 = o.observables()
+        assert o.step(1) == 0
+        ob1 = o.observables()
+        force = ob1[25:28] + ob1[22:25]
+        assert np.abs(force).max() > 1e-6              # the frontier makes it non-zero
+        half = ob0[32:35] - ob0[2:5]
+        assert np.abs(half - 0.5 * force).max() < 1e-14 * (ob0[0] + ob0[1])
+    # the link-force magnitude summed over the spheres
+    assert abs(ob1[35] - o.particles()[:, O.REC["flabs"]].sum()) < 1e-12 * ob1[35]
+
+
 def test_ladd_drag_and_braking_torque_signs():
     # a sphere held at rest in a uniform stream is dragged along the stream
     L = 20
