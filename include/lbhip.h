@@ -133,12 +133,15 @@ typedef struct lb_buffers {
   lb_sizes bytes;    /* allocated sizes; each must be >= lb_required_sizes()        */
 } lb_buffers;
 
-/* Observables of the current state (FP64), Sec. 3 statistics / App. C keys. */
+/* Observables of the current state (FP64): the statistics of Sec. 3 and the
+ * output keys of App. C (masses, momenta, extrema, particle momentum and
+ * energies). */
 typedef struct lb_obs {
   int64_t step;          /* steps taken since lb_init                                 */
   int64_t fluid_nodes;   /* fluid nodes of the current map                            */
   double  mass[2];       /* sum over fluid nodes of rho_k                              */
-  double  momentum[3];   /* sum over fluid nodes and components of sum_i f_i c_i      */
+  double  momentum[3];   /* bare momentum: sum over fluid nodes and components of
+                            sum_i f_i c_i                                              */
   double  rho_min[2], rho_max[2];
   double  u_max;         /* max over fluid nodes of |u| (mixture velocity, Eq. scvel)  */
   double  particle_momentum[3];
@@ -147,6 +150,12 @@ typedef struct lb_obs {
   int32_t nparticles;
   int32_t flags;         /* bit 0: particle speed exceeded, bit 1: non-finite fluid,
                             bit 2: frontier list overflow (ruled out by its sizing)    */
+  double  phys_momentum[3]; /* physical momentum (Sec. 2.3, after Eq. lbsbgk): the bare
+                            momentum plus half the force density summed over the fluid,
+                            F_k = Shan-Chen force (Eq. shanchen, virtual densities of the
+                            current map on the frontier) + rho_k g                     */
+  double  flink_abs;     /* sum over spheres and links of |F_link| (Eq. LADDFORCE) of
+                            the last step: the scale of the particle force tolerances  */
 } lb_obs;
 
 /* Per-sphere record of lb_get_particles / lb_set_particles, FP64, in this order. */
@@ -210,7 +219,8 @@ int lb_add_particles(struct lb_ctx* ctx, int32_t n, const double* x, const doubl
  * Errors: LB_E_ARG, LB_E_HIP, LB_E_CAPACITY. */
 int lb_step(struct lb_ctx* ctx, int32_t nsteps);
 
-/* FP64 observables of the current state. Synchronises.
+/* FP64 observables of the current state. Recomputes the pseudo-potential of
+ * the current state for the force density (as lb_get_psi). Synchronises.
  * Errors: LB_E_PARTICLE_SPEED / LB_E_NONFINITE / LB_E_CAPACITY (node-list
  * overflow) when flagged (out is still filled). */
 int lb_observables(struct lb_ctx* ctx, lb_obs* out);
@@ -234,9 +244,17 @@ int lb_set_populations(struct lb_ctx* ctx, const double* f);
  * host int32 [N]. Synchronises. */
 int lb_get_owner(struct lb_ctx* ctx, int32_t* owner);
 
-/* Sphere records (LB_PREC doubles each), host FP64 [nparticles][LB_PREC].
- * lb_set_particles writes x, v, w, q, FPREV, TPREV, HAVEPREV of existing
- * spheres and re-rasterises the map without fluid-node events. Synchronises. */
+/* Sphere records (Sec. 2.4-2.5 particle state; LB_PREC doubles each), host
+ * FP64 [nparticles][LB_PREC]. lb_set_particles writes v, w, q, FPREV, TPREV
+ * and HAVEPREV of the existing spheres; every value must be finite and q
+ * non-zero (LB_E_ARG). Before the first step it also takes new positions
+ * (wrapped into the box), checks them like lb_add_particles (LB_E_OVERLAP)
+ * and re-rasterises the map: nodes that a moved sphere frees keep the
+ * populations they held before the spheres covered them (those of lb_init
+ * unless lb_set_populations changed them). After the first step a position
+ * that differs from the stored one is refused (LB_E_STATE): a moved sphere
+ * needs the node events of a step; lb_set_state replaces a whole state.
+ * Nothing is changed when a check fails. Synchronises. */
 int lb_get_particles(struct lb_ctx* ctx, double* rec);
 int lb_set_particles(struct lb_ctx* ctx, const double* rec);
 int lb_num_particles(const struct lb_ctx* ctx);

@@ -141,6 +141,8 @@ def lib():
         L.lbo_loss.restype = C.c_double
         L.lbo_loss_tangent.argtypes = [C.POINTER(_Params), dp, C.c_int32, dp, C.c_int32,
                                        C.c_double, dp, dp, dp, dp]
+        L.lbo_psi_tangent.argtypes = [C.POINTER(_Params), dp, C.c_int32, dp, C.c_int32,
+                                      C.c_double, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -277,6 +279,26 @@ def loss_tangent(params: Params, rho0: np.ndarray, nsteps: int, dG: float = 0.0,
     if rc != 0:
         raise ValueError(f"lbo_loss_tangent: {rc}")
     return L.value, dL.value
+
+
+def psi_tangent(params: Params, rho0: np.ndarray, nsteps: int, dG: float = 0.0,
+                dg: Sequence[float] = (0.0, 0.0, 0.0), drhoA: Optional[np.ndarray] = None,
+                x: Optional[np.ndarray] = None):
+    """(psi, dpsi) [ncomp][N] of the final state of a dual-number run of nsteps
+    from f = f_eq(rho0, 0): the tangent-linear map applied to (dG, dg, drhoA)."""
+    cp = params.to_c()
+    r = _f64(rho0).reshape(params.ncomp, params.N)
+    dgv = _f64(dg)
+    dr = None if drhoA is None else _f64(drhoA).reshape(params.N)
+    xx = None if x is None else _f64(x).reshape(-1, 3)
+    np_ = 0 if xx is None else xx.shape[0]
+    psi = np.zeros((params.ncomp, params.N))
+    dpsi = np.zeros((params.ncomp, params.N))
+    rc = lib().lbo_psi_tangent(C.byref(cp), _dp(r), np_, _dp(xx), nsteps, dG, _dp(dgv),
+                               _dp(dr), _dp(psi), _dp(dpsi))
+    if rc != 0:
+        raise ValueError(f"lbo_psi_tangent: {rc}")
+    return psi, dpsi
 
 
 # record offsets (see lbo.h)

@@ -1065,4 +1065,35 @@ int lbo_loss_tangent(const lbo_params* p, const double* rho0, int32_t np, const 
   return LBO_OK;
 }
 
+int lbo_psi_tangent(const lbo_params* p, const double* rho0, int32_t np, const double* x,
+                    int32_t nsteps, double dG, const double* dg, const double* drhoA,
+                    double* psi, double* dpsi) {
+  if (!valid(p) || !rho0 || !psi || !dpsi || (np > 0 && (!x || !p->particles_fixed)))
+    return LBO_E_ARG;
+  Sim<Dual> S;
+  S.setup(*p);
+  S.G = Dual(p->G, dG);
+  for (int a = 0; a < 3; ++a) S.g[a] = Dual(p->g[a], dg ? dg[a] : 0.0);
+  std::vector<Dual> r0(size_t(S.K) * S.N);
+  for (int64_t m = 0; m < int64_t(r0.size()); ++m) {
+    double d = (drhoA && m < S.N) ? drhoA[m] : 0.0;
+    r0[m] = Dual(rho0[m], d);
+  }
+  S.init_fields(r0.data(), nullptr);
+  if (np > 0) S.add_particles(np, x, nullptr, nullptr, nullptr);
+  for (int t = 0; t < nsteps; ++t) {
+    int rc = S.step();
+    if (rc != LBO_OK) return rc;
+  }
+  // the pseudo-potential of the final state, as the loss sees it
+  std::vector<Dual> rho, j, u, rt;
+  S.moments(S.own, rho, j, u);
+  S.fill(S.own, rho, rt);
+  for (size_t m = 0; m < rt.size(); ++m) {
+    psi[m] = rt[m].v;
+    dpsi[m] = rt[m].d;
+  }
+  return LBO_OK;
+}
+
 }  // extern "C"

@@ -136,6 +136,15 @@ int     lbo_loss_tangent(const lbo_params* p, const double* rho0, int32_t np,
                          const double* dg /* [3] */, const double* drhoA /* [N] or NULL */,
                          double* L, double* dL);
 
+/* Forward-mode run as lbo_loss_tangent, returning instead the pseudo-potential
+ * psi_k(n) of the final state (as lbo_get_psi) and its directional derivative
+ * dpsi_k(n), both [ncomp][N]: the tangent-linear map of the whole run applied
+ * to (dG, dg, drhoA). */
+int     lbo_psi_tangent(const lbo_params* p, const double* rho0, int32_t np,
+                        const double* x, int32_t nsteps, double dG,
+                        const double* dg /* [3] */, const double* drhoA /* [N] or NULL */,
+                        double* psi, double* dpsi);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,7 +69,8 @@ class lb_obs(C.Structure):
                 ("rho_max", C.c_double * 2), ("u_max", C.c_double),
                 ("particle_momentum", C.c_double * 3), ("particle_ke", C.c_double),
                 ("particle_ke_rot", C.c_double), ("nparticles", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("phys_momentum", C.c_double * 3),
+                ("flink_abs", C.c_double)]
 
 
 class LBError(RuntimeError):

@@ -2,11 +2,18 @@
 
 Each csrc/*.hip file is compiled to an object with hipcc for gfx950 only and
 the objects are linked into one shared library exporting the C interface of
-include/lbhip.h. Packed FP32 instructions are disabled for all device code.
+include/lbhip.h.
+
+Packed FP32 instructions (v_pk_add_f32, v_pk_mul_f32, v_pk_fma_f32) are kept
+out of all device code: the target feature -packed-fp32-ops is passed to the
+gfx950 device pass (the x86 host pass does not know the feature and says it
+ignores it, which is harmless). The build then compiles every source once
+more to gfx950 assembly and fails if any packed FP32 instruction is there.
 """
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -30,6 +37,27 @@ SOURCES = ["lb_fluid.hip", "lb_particles.hip", "lb_adjoint.hip", "lb_domain.hip"
 LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 
 
+PACKED_FP32 = re.compile(r"\bv_pk_(add|mul|fma)_f32\b")
+
+
+def device_asm(src_path: str, out: str, flags=None) -> str:
+    """gfx950 assembly of one source (device pass only), as text."""
+    cmd = [HIPCC, *(FLAGS if flags is None else flags), "--cuda-device-only", "-S", src_path,
+           "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed for {src_path}:\n{r.stdout}\n{r.stderr}")
+    with open(out) as fh:
+        return fh.read()
+
+
+def _check_no_packed_fp32(src: str) -> None:
+    asm = device_asm(os.path.join(CSRC, src), os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".s"))
+    found = sorted(set(m.group(0) for m in PACKED_FP32.finditer(asm)))
+    if found:
+        raise RuntimeError(f"{src}: packed FP32 instructions in the device code: {found}")
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -48,6 +76,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OBJ_DIR, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        list(ex.map(_check_no_packed_fp32, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, *LIBS, "-o", tmp]
     if verbose:

@@ -407,38 +407,33 @@ int lb_init(const lb_params* p, const lb_buffers* b, const double* rho0, const d
 
 int lb_num_particles(const lb_ctx* c) { return c ? c->nparticles : 0; }
 
-int lb_add_particles(lb_ctx* c, int32_t n, const double* x, const double* v, const double* w,
-                     const double* q) {
-  if (!c) return LB_E_ARG;
-  if (n < 0 || (n > 0 && !x)) return fail(c, LB_E_ARG, "bad sphere arrays");
-  if (c->step != 0) return fail(c, LB_E_STATE, "spheres can only be added before the first step");
-  if (n == 0) return LB_OK;
-  if (c->nparticles + n > c->P.max_particles)
-    return fail(c, LB_E_CAPACITY, "more spheres than max_particles");
+namespace {
+
+// A coordinate taken into [0, L): fmod leaves (-L, L), and a tiny negative
+// value plus L rounds to L itself, which is wrapped again.
+double wrap_coord(double v, double L) {
+  double r = std::fmod(v, L);
+  if (r < 0) r += L;
+  if (r >= L) r -= L;
+  return r;
+}
+
+// Checks of a set of sphere records before they are rasterised: records
+// [P0, P1) of st are new; each must stay clear of the wall layers, and no two
+// centres may be closer than 2R unless both are old (hash grid of cell side
+// 2R). Returns LB_OK or the status, with the reason in why.
+int check_placement(const lb_ctx* c, const std::vector<double>& st, int P0, int P1,
+                    std::string& why) {
   const double L[3] = {double(c->geo.nx), double(c->geo.ny), double(c->geo.nz)};
   const double R = c->P.radius;
-  // host copy of the existing records plus the new ones
-  const int P0 = c->nparticles, P1 = P0 + n;
-  std::vector<double> st(size_t(P1) * PSTRIDE, 0.0);
-  if (P0 > 0)
-    HIPCHK(c, hipMemcpy(st.data(), pstate(c), size_t(P0) * PSTRIDE * sizeof(double),
-                        hipMemcpyDeviceToHost));
-  for (int i = 0; i < n; ++i) {
-    double* r = &st[size_t(P0 + i) * PSTRIDE];
-    for (int d = 0; d < 3; ++d) {
-      if (!is_finite(x[3 * i + d])) return fail(c, LB_E_ARG, "non-finite sphere position");
-      double xv = std::fmod(x[3 * i + d], L[d]);
-      if (xv < 0) xv += L[d];
-      if (xv >= L[d]) xv -= L[d];
-      r[PS_X + d] = r[PS_XRA + d] = r[PS_XRB + d] = xv;
-      r[PS_V + d] = v ? v[3 * i + d] : 0.0;
-      r[PS_W + d] = w ? w[3 * i + d] : 0.0;
+  if (c->P.walls)
+    for (int p = P0; p < P1; ++p) {
+      const double z = st[size_t(p) * PSTRIDE + PS_X + 2];
+      if (z - R < 0.5 || z + R > L[2] - 1.5) {
+        why = "a sphere reaches a wall layer";
+        return LB_E_OVERLAP;
+      }
     }
-    for (int e = 0; e < 4; ++e) r[PS_Q + e] = q ? q[4 * i + e] : (e == 0 ? 1.0 : 0.0);
-    if (c->P.walls && (r[PS_X + 2] - R < 0.5 || r[PS_X + 2] + R > L[2] - 1.5))
-      return fail(c, LB_E_OVERLAP, "a sphere reaches a wall layer");
-  }
-  // overlap check through a hash grid of cell side 2R
   const double side = 2.0 * R;
   int nc[3];
   for (int d = 0; d < 3; ++d) nc[d] = std::max(1, int(L[d] / side));
@@ -466,12 +461,56 @@ int lb_add_particles(lb_ctx* c, int32_t n, const double* x, const double* v, con
               dd -= L[d] * std::nearbyint(dd / L[d]);
               d2 += dd * dd;
             }
-            if (d2 < side * side) return fail(c, LB_E_OVERLAP, "sphere centres closer than 2R");
+            if (d2 < side * side) {
+              why = "sphere centres closer than 2R";
+              return LB_E_OVERLAP;
+            }
           }
         }
     auto& cell = grid[key(ci)];
     if (std::find(cell.begin(), cell.end(), p) == cell.end()) cell.push_back(p);
   }
+  return LB_OK;
+}
+
+}  // namespace
+
+int lb_add_particles(lb_ctx* c, int32_t n, const double* x, const double* v, const double* w,
+                     const double* q) {
+  if (!c) return LB_E_ARG;
+  if (n < 0 || (n > 0 && !x)) return fail(c, LB_E_ARG, "bad sphere arrays");
+  if (c->step != 0) return fail(c, LB_E_STATE, "spheres can only be added before the first step");
+  if (n == 0) return LB_OK;
+  if (c->nparticles + n > c->P.max_particles)
+    return fail(c, LB_E_CAPACITY, "more spheres than max_particles");
+  const double L[3] = {double(c->geo.nx), double(c->geo.ny), double(c->geo.nz)};
+  // host copy of the existing records plus the new ones
+  const int P0 = c->nparticles, P1 = P0 + n;
+  std::vector<double> st(size_t(P1) * PSTRIDE, 0.0);
+  if (P0 > 0)
+    HIPCHK(c, hipMemcpy(st.data(), pstate(c), size_t(P0) * PSTRIDE * sizeof(double),
+                        hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) {
+    double* r = &st[size_t(P0 + i) * PSTRIDE];
+    for (int d = 0; d < 3; ++d) {
+      if (!is_finite(x[3 * i + d]) || (v && !is_finite(v[3 * i + d])) ||
+          (w && !is_finite(w[3 * i + d])))
+        return fail(c, LB_E_ARG, "non-finite sphere position or velocity");
+      const double xv = wrap_coord(x[3 * i + d], L[d]);
+      r[PS_X + d] = r[PS_XRA + d] = r[PS_XRB + d] = xv;
+      r[PS_V + d] = v ? v[3 * i + d] : 0.0;
+      r[PS_W + d] = w ? w[3 * i + d] : 0.0;
+    }
+    double qn = 0;
+    for (int e = 0; e < 4; ++e) {
+      r[PS_Q + e] = q ? q[4 * i + e] : (e == 0 ? 1.0 : 0.0);
+      qn += r[PS_Q + e] * r[PS_Q + e];
+    }
+    if (!is_finite(qn) || !(qn > 0.0)) return fail(c, LB_E_ARG, "bad sphere quaternion");
+  }
+  std::string why;
+  const int rc = check_placement(c, st, P0, P1, why);
+  if (rc != LB_OK) return fail(c, rc, why);
   HIPCHK(c, hipMemcpy(pstate(c) + size_t(P0) * PSTRIDE, &st[size_t(P0) * PSTRIDE],
                       size_t(n) * PSTRIDE * sizeof(double), hipMemcpyHostToDevice));
   c->nparticles = P1;
@@ -645,19 +684,36 @@ int lb_sync(lb_ctx* c) {
   return LB_OK;
 }
 
+// Pseudo-potential of the current state on its map: moments, then the
+// virtual densities of the frontier (the sphere fill leaves the force
+// accumulators alone).
+int current_psi(lb_ctx* c) {
+  HIPCHK(c, launch_density(c, c->B.f[c->cur]));
+  const uint16_t* own = owner_now(c);
+  if (c->nparticles > 0) HIPCHK(c, launch_fill_particles(c, own, false));
+  if (c->P.walls) HIPCHK(c, launch_fill_walls(c, own));
+  return LB_OK;
+}
+
 int lb_observables(lb_ctx* c, lb_obs* o) {
   if (!c || !o) return LB_E_ARG;
   double* red = reinterpret_cast<double*>(wptr(c, c->wl.red_out));
+  // the force density of the physical momentum needs the pseudo-potential
+  const int rc = current_psi(c);
+  if (rc != LB_OK) return rc;
   HIPCHK(c, launch_reduce(c, red));
   double r[RED_N];
   int32_t flags[3];
   HIPCHK(c, hipMemcpyAsync(r, red, sizeof(r), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(flags, wptr(c, c->wl.flags), sizeof(flags), hipMemcpyDeviceToHost,
                            c->stream));
-  std::vector<double> st(size_t(c->nparticles) * PSTRIDE);
-  if (c->nparticles)
+  std::vector<double> st(size_t(c->nparticles) * PSTRIDE), ac(size_t(c->nparticles) * ASTRIDE);
+  if (c->nparticles) {
     HIPCHK(c, hipMemcpyAsync(st.data(), pstate(c), st.size() * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ac.data(), pacc(c), ac.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::memset(o, 0, sizeof(*o));
   o->step = c->step;
@@ -689,6 +745,17 @@ int lb_observables(lb_ctx* c, lb_obs* o) {
   o->particle_ke_rot = nsum([&](const double* P) {
     return 0.5 * c->inertia * (P[PS_W] * P[PS_W] + P[PS_W + 1] * P[PS_W + 1] + P[PS_W + 2] * P[PS_W + 2]);
   });
+  for (int d = 0; d < 3; ++d) o->phys_momentum[d] = r[2 + d] + 0.5 * r[12 + d];
+  {
+    double s = 0, comp = 0;
+    for (int p = 0; p < c->nparticles; ++p) {
+      const double x = ac[size_t(p) * ASTRIDE + AC_FLABS];
+      const double t = s + x;
+      comp += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
+      s = t;
+    }
+    o->flink_abs = s + comp;
+  }
   o->flags = (flags[0] ? 1 : 0) | (r[11] > 0 || !std::isfinite(r[0]) ? 2 : 0) | (flags[2] ? 4 : 0);
   if (o->flags & 1) return fail(c, LB_E_PARTICLE_SPEED, "sphere speed exceeded 1/2 per step");
   if (o->flags & 2) return fail(c, LB_E_NONFINITE, "non-finite populations");
@@ -719,12 +786,8 @@ int lb_get_fields(lb_ctx* c, double* rho, double* u) {
 
 int lb_get_psi(lb_ctx* c, double* psi) {
   if (!c || !psi) return LB_E_ARG;
-  // psi of the current state on the current map: moments, then the fills
-  // (the sphere fill runs without touching the force accumulators)
-  HIPCHK(c, launch_density(c, c->B.f[c->cur]));
-  const uint16_t* own = owner_now(c);
-  if (c->nparticles > 0) HIPCHK(c, launch_fill_particles(c, own, false));
-  if (c->P.walls) HIPCHK(c, launch_fill_walls(c, own));
+  const int rc = current_psi(c);
+  if (rc != LB_OK) return rc;
   const uint32_t N = c->geo.N, chunk = chunk_nodes(c, 1);
   double* stage = reinterpret_cast<double*>(wptr(c, c->wl.staging));
   for (int k = 0; k < c->geo.ncomp; ++k)
@@ -828,27 +891,52 @@ int lb_set_particles(lb_ctx* c, const double* rec) {
   if (!c || (!rec && c->nparticles)) return LB_E_ARG;
   const int np = c->nparticles;
   if (np == 0) return LB_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   std::vector<double> st(size_t(np) * PSTRIDE);
   HIPCHK(c, hipMemcpy(st.data(), pstate(c), st.size() * sizeof(double), hipMemcpyDeviceToHost));
   const double L[3] = {double(c->geo.nx), double(c->geo.ny), double(c->geo.nz)};
+  const bool before_first_step = c->step == 0;
   for (int p = 0; p < np; ++p) {
     double* S = &st[size_t(p) * PSTRIDE];
     const double* o = rec + size_t(p) * LB_PREC;
+    double qn = 0;
+    for (int e = 0; e < 4; ++e) qn += o[LB_P_Q + e] * o[LB_P_Q + e];
+    bool finite = is_finite(qn) && is_finite(o[LB_P_HAVEPREV]);
+    for (int d = 0; d < 3; ++d)
+      finite = finite && is_finite(o[LB_P_X + d]) && is_finite(o[LB_P_V + d]) &&
+               is_finite(o[LB_P_W + d]) && is_finite(o[LB_P_FPREV + d]) &&
+               is_finite(o[LB_P_TPREV + d]);
+    if (!finite) return fail(c, LB_E_ARG, "non-finite value in a sphere record");
+    if (!(qn > 0.0)) return fail(c, LB_E_ARG, "bad sphere quaternion");
     for (int d = 0; d < 3; ++d) {
-      double xv = std::fmod(o[LB_P_X + d], L[d]);
-      if (xv < 0) xv += L[d];
-      S[PS_X + d] = S[PS_XRA + d] = S[PS_XRB + d] = xv;
+      const double xv = wrap_coord(o[LB_P_X + d], L[d]);
+      if (before_first_step) {
+        S[PS_X + d] = S[PS_XRA + d] = S[PS_XRB + d] = xv;
+      } else if (xv != S[PS_X + d]) {
+        // a moved sphere frees and covers nodes, which needs the node
+        // events of a step (or a whole state, lb_set_state)
+        return fail(c, LB_E_STATE, "sphere positions can only change before the first step");
+      }
       S[PS_V + d] = o[LB_P_V + d];
       S[PS_W + d] = o[LB_P_W + d];
       S[PS_FPREV + d] = o[LB_P_FPREV + d];
       S[PS_TPREV + d] = o[LB_P_TPREV + d];
     }
     for (int e = 0; e < 4; ++e) S[PS_Q + e] = o[LB_P_Q + e];
-    S[PS_HAVEPREV] = o[LB_P_HAVEPREV];
+    S[PS_HAVEPREV] = o[LB_P_HAVEPREV] != 0.0 ? 1.0 : 0.0;
+  }
+  if (before_first_step) {
+    std::string why;
+    const int rc = check_placement(c, st, 0, np, why);
+    if (rc != LB_OK) return fail(c, rc, why);
   }
   HIPCHK(c, hipMemcpy(pstate(c), st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(c, launch_raster_full(c, static_cast<uint16_t*>(c->B.owner[0])));
-  HIPCHK(c, launch_raster_full(c, static_cast<uint16_t*>(c->B.owner[1])));
+  if (before_first_step) {
+    // the fluid nodes of the new map start from the populations of lb_init
+    // (no population was ever stepped); nodes that become solid are dropped
+    HIPCHK(c, launch_raster_full(c, static_cast<uint16_t*>(c->B.owner[0])));
+    HIPCHK(c, launch_raster_full(c, static_cast<uint16_t*>(c->B.owner[1])));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LB_OK;
 }

@@ -709,13 +709,17 @@ __global__ void k_owner_to_int(const uint16_t* __restrict__ owner, uint32_t firs
 // ---------------------------------------------------------------------------
 // Observables: deterministic two-level FP64 reduction over the fluid nodes.
 // partial[b][*]: 0,1 sum drho_k; 2..4 momentum; 5,6 min drho_k; 7,8 max drho_k;
-// 9 max |u|; 10 fluid nodes; 11 non-finite count.
+// 9 max |u|; 10 fluid nodes; 11 non-finite count; 12..14 sum over components
+// of the force density F_k = -G s rho_k sum_i w_i psi_kbar(n + c_i) c_i + rho_k g
+// (Eq. shanchen), from the pseudo-potential of the current state.
 // ---------------------------------------------------------------------------
+constexpr int RED_USED = 15;
 template <typename real>
 __global__ void __launch_bounds__(BLOCK)
-k_reduce_partials(const real* __restrict__ f, const uint16_t* __restrict__ owner, uint32_t nx,
-                  uint32_t ny, uint32_t nz, int ncomp, double r0a, double r0b, double it0,
-                  double it1, double* __restrict__ partial) {
+k_reduce_partials(const real* __restrict__ f, const real* __restrict__ psi,
+                  const uint16_t* __restrict__ owner, uint32_t nx, uint32_t ny, uint32_t nz,
+                  int ncomp, double r0a, double r0b, double it0, double it1, double Gs, double gx,
+                  double gy, double gz, double* __restrict__ partial) {
   const uint32_t N = nx * ny * nz;
   double v[RED_N];
   for (int c = 0; c < RED_N; ++c) v[c] = 0.0;
@@ -743,14 +747,30 @@ k_reduce_partials(const real* __restrict__ f, const uint16_t* __restrict__ owner
       if (!isfinite(s)) v[11] += 1.0;
       const double it = k == 0 ? it0 : it1;
       for (int c = 0; c < 3; ++c) num[c] += j[c] * it;
-      den += ((k == 0 ? r0a : r0b) + s) * it;
+      const double rk = (k == 0 ? r0a : r0b) + s;
+      den += rk * it;
+      // force density; the psi reference cancels in the stencil because
+      // every neighbour of a fluid node is fluid or a frontier solid
+      double sc[3] = {0, 0, 0};
+      if (ncomp == 2) {
+        const real* pk = psi + size_t(1 - k) * N;
+        for (int i = 1; i < Q; ++i) {
+          const double w = double(pk[nb.push(i)]) * WQ[i];
+          sc[0] += w * CX[i];
+          sc[1] += w * CY[i];
+          sc[2] += w * CZ[i];
+        }
+      }
+      v[12] += rk * (gx - Gs * sc[0]);
+      v[13] += rk * (gy - Gs * sc[1]);
+      v[14] += rk * (gz - Gs * sc[2]);
     }
     const double ux = num[0] / den, uy = num[1] / den, uz = num[2] / den;
     v[9] = fmax(v[9], sqrt(ux * ux + uy * uy + uz * uz));
     v[10] += 1.0;
   }
   __shared__ double sh[BLOCK];
-  for (int c = 0; c < 12; ++c) {
+  for (int c = 0; c < RED_USED; ++c) {
     sh[threadIdx.x] = v[c];
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
@@ -771,7 +791,7 @@ k_reduce_partials(const real* __restrict__ f, const uint16_t* __restrict__ owner
 __global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* __restrict__ partial,
                                                         int nb, double* __restrict__ out) {
   __shared__ double sh[BLOCK];
-  for (int c = 0; c < 12; ++c) {
+  for (int c = 0; c < RED_USED; ++c) {
     double acc = (c == 5 || c == 6) ? 1e300 : (c == 7 || c == 8 || c == 9) ? -1e300 : 0.0;
     for (int b = threadIdx.x; b < nb; b += BLOCK) {
       const double o = partial[size_t(b) * RED_N + c];
@@ -1062,16 +1082,19 @@ hipError_t launch_reduce(lb_ctx* c, double* out_dev) {
   const int kb = g.ncomp == 2 ? 1 : 0;
   double* partial = reinterpret_cast<double*>(wptr(c, c->wl.partials));
   const int nb = int(std::min<uint64_t>(RED_BLOCKS, nblocks(g.N)));
+  const double Gs = P.G * P.sc_norm;
   if (fp64(c))
     hipLaunchKernelGGL(k_reduce_partials<double>, dim3(nb), dim3(BLOCK), 0, c->stream,
-                       static_cast<const double*>(c->B.f[c->cur]), cur_owner(c), g.nx, g.ny,
-                       g.nz, g.ncomp, P.rho0[0], P.rho0[kb], 1.0 / P.tau[0], 1.0 / P.tau[kb],
-                       partial);
+                       static_cast<const double*>(c->B.f[c->cur]),
+                       static_cast<const double*>(c->B.rho), cur_owner(c), g.nx, g.ny, g.nz,
+                       g.ncomp, P.rho0[0], P.rho0[kb], 1.0 / P.tau[0], 1.0 / P.tau[kb], Gs,
+                       P.g[0], P.g[1], P.g[2], partial);
   else
     hipLaunchKernelGGL(k_reduce_partials<float>, dim3(nb), dim3(BLOCK), 0, c->stream,
-                       static_cast<const float*>(c->B.f[c->cur]), cur_owner(c), g.nx, g.ny,
-                       g.nz, g.ncomp, P.rho0[0], P.rho0[kb], 1.0 / P.tau[0], 1.0 / P.tau[kb],
-                       partial);
+                       static_cast<const float*>(c->B.f[c->cur]),
+                       static_cast<const float*>(c->B.rho), cur_owner(c), g.nx, g.ny, g.nz,
+                       g.ncomp, P.rho0[0], P.rho0[kb], 1.0 / P.tau[0], 1.0 / P.tau[kb], Gs,
+                       P.g[0], P.g[1], P.g[2], partial);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, c->stream, partial, nb, out_dev);
   return hipGetLastError();
 }

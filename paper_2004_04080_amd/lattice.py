@@ -135,6 +135,8 @@ class Observables:
     particle_ke_rot: float
     nparticles: int
     flags: int
+    phys_momentum: np.ndarray = None
+    flink_abs: float = 0.0
     status: int = 0
 
 
@@ -231,7 +233,8 @@ class Lattice:
         return Observables(o.step, o.fluid_nodes, np.array(o.mass[:]), np.array(o.momentum[:]),
                            np.array(o.rho_min[:]), np.array(o.rho_max[:]), o.u_max,
                            np.array(o.particle_momentum[:]), o.particle_ke, o.particle_ke_rot,
-                           o.nparticles, o.flags, rc)
+                           o.nparticles, o.flags, np.array(o.phys_momentum[:]), o.flink_abs,
+                           rc)
 
     def fields(self):
         rho = np.empty((self.params.ncomp, self.N))

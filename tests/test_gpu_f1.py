@@ -2,8 +2,8 @@
 oracle: pairs of spheres approaching within the lubrication range, with the
 orientation-dependent wetting of the benchmark input (108 +- 5 degrees,
 constants 0.1), moving and rotating. FP64 at the bounds of the other
-moving-sphere tests (fields 1e-12, sphere state 1e-11), FP32 step parity at
-1e-5."""
+moving-sphere tests (fields, sphere state and force terms 1e-12), FP32 step
+parity at 1e-5."""
 import numpy as np
 import pytest
 
@@ -60,9 +60,9 @@ def test_lubrication_and_janus_fp64():
         e.pop("df")
         for k, val in e.items():
             assert val <= 1e-12, (h, k, val)
-        assert ep["x"] < 1e-11 and ep["v"] < 1e-11 and ep["w"] < 1e-11 and ep["q"] < 1e-11
+        assert ep["x"] < 1e-12 and ep["v"] < 1e-12 and ep["w"] < 1e-12 and ep["q"] < 1e-12
         for k in ("FH", "FSC", "TSC", "Fliq", "Tliq"):
-            assert ep[k] < 1e-11, (h, k, ep[k])
+            assert ep[k] < 1e-12, (h, k, ep[k])
     # the lubrication force was active
     assert np.abs(o.particles()[:, 31:34]).max() > 1e-5
 

@@ -4,7 +4,8 @@ fluids, 32,000 moving spheres of radius 5.5) and the confined box
 with the parameters that bench.py uses for it.
 
 The oracle cannot step the whole box, so it steps windows of it. After a few
-steps on the GPU, the state (FP32 populations read out as FP64, the map and
+steps on the GPU (or 200, when the components have begun to separate and the
+spheres move, with windows centred on node events), the state (FP32 populations read out as FP64, the map and
 the sphere records) of four 80^3 windows is handed to the oracle, which
 steps each window once as a periodic box of its own. One step reaches only a
 few nodes: streaming, the pseudo-potential stencil, the frontier fill and the
@@ -31,6 +32,7 @@ W = 80          # window edge
 MARGIN = 16     # nodes next to a window face that are not compared
 TOL32 = 1e-5
 TOL32_U = 5e-5  # derivation in tests/test_gpu_parity.py
+TOL64 = 1e-12
 
 
 def _window_index(origin, shape, win):
@@ -43,20 +45,52 @@ def _eps(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def _window_parity(name, origins):
+def _event_origins(lat, shape, win, per_kind=2):
+    """Window origins centred on nodes that the next step creates or destroys:
+    the step is taken once from a snapshot to find them, and the snapshot is
+    restored."""
+    blob = lat.state()
+    own_a = lat.owner()
+    lat.step(1)
+    own_b = lat.owner()
+    lat.set_state(blob)
+    del blob
+    created = np.flatnonzero((own_a > 0) & (own_b == 0))
+    destroyed = np.flatnonzero((own_a == 0) & (own_b > 0))
+    print(f"[fullsize] next step: {created.size} nodes created, {destroyed.size} destroyed",
+          flush=True)
+    assert created.size > 0 and destroyed.size > 0
+    rng = np.random.default_rng(9)
+    origins = []
+    for nodes in (created, destroyed):
+        for n in rng.choice(nodes, size=min(per_kind, nodes.size), replace=False):
+            xyz = (n % shape[0], (n // shape[0]) % shape[1], n // (shape[0] * shape[1]))
+            origins.append(tuple(int((xyz[d] - win[d] // 2) % shape[d]) if win[d] < shape[d]
+                                 else 0 for d in range(3)))
+    return origins
+
+
+def _window_parity(name, origins, warm=3, precision="fp32", events=False):
     """Step the bench state of workload `name` on the GPU, then one step of
     each window in the oracle; compare the window interiors. With walls a
     window spans the whole z height with the real walls, and only its x and y
-    faces are periodic wraps (and excluded from the comparison)."""
+    faces are periodic wraps (and excluded from the comparison). With events
+    the windows are centred on nodes that the compared step creates or
+    destroys, and each window interior must hold node events."""
     import bench
     from paper_2004_04080_amd import Lattice
     w = synth.workload(name)
     shape = (w.nx, w.ny, w.nz)
     win = (W, W, w.nz if w.walls else W)
-    print(f"[fullsize] building the {shape} state of {name}", flush=True)
-    lat = Lattice(bench.params_for(w, "fp32"), w.densities())
+    tol = TOL32 if precision == "fp32" else TOL64
+    tol_u = TOL32_U if precision == "fp32" else TOL64
+    print(f"[fullsize] building the {shape} state of {name} ({precision}), {warm} steps",
+          flush=True)
+    lat = Lattice(bench.params_for(w, precision), w.densities())
     lat.add_particles(w.centres())
-    lat.step(3)
+    lat.step(warm)
+    if events:
+        origins = _event_origins(lat, shape, win)
     idx = [_window_index(o, shape, win) for o in origins]
     f = lat.populations()
     f0 = [f[:, :, i] for i in idx]
@@ -133,11 +167,14 @@ def _window_parity(name, origins):
              "rho0": _eps(rg[0], ro[0]), "rho1": _eps(rg[1], ro[1]),
              "phi": _eps(rg[0] - rg[1], ro[0] - ro[1]),
              "u": _eps(u1[k][m], o.u()[m])}
-        print(f"[fullsize] {name} window {org}: {m.sum()} fluid nodes, "
+        nev = int(((own0[k] != 0) != (own1[k] != 0))[inner].sum())
+        print(f"[fullsize] {name} window {org}: {m.sum()} fluid nodes, {nev} node events, "
               + " ".join(f"{a} {b:.1e}" for a, b in e.items()), flush=True)
+        if events:
+            assert nev > 0, f"no node event inside window {org}"
         for key in ("f", "rho0", "rho1", "phi"):
-            assert e[key] <= TOL32, (org, key, e[key])
-        assert e["u"] <= TOL32_U, (org, e["u"])
+            assert e[key] <= tol, (org, key, e[key])
+        assert e["u"] <= tol_u, (org, e["u"])
 
         # spheres whose links and events all fall in the compared interior
         lo = np.where(wrapped, MARGIN + R + 2.0, -np.inf)
@@ -150,7 +187,7 @@ def _window_parity(name, origins):
             scale = op[REC["flabs"]]
             for key in ("Fliq", "Tliq", "FSC", "TSC", "Fd", "Td", "Fc", "Tc"):
                 err = np.abs(gp[REC[key]:REC[key] + 3] - op[REC[key]:REC[key] + 3]).max() / scale
-                assert err < TOL32, (org, int(sel[j]), key, err)
+                assert err < tol, (org, int(sel[j]), key, err)
         nspheres_checked += len(whole)
     print(f"[fullsize] {name}: spheres compared: {nspheres_checked}", flush=True)
     assert nspheres_checked > 0
@@ -169,3 +206,12 @@ def test_confined_box_one_step_parity_on_windows():
     rng = np.random.default_rng(6)
     origins = [(int(rng.integers(0, 512)), int(rng.integers(0, 512)), 0) for _ in range(3)]
     _window_parity("C4", origins)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_full_size_demixed_state_with_node_events(precision):
+    """The bench box after 200 steps, when the components have started to
+    separate and the spheres move: one step compared on four windows centred
+    on nodes that the step creates or destroys (two of each), in FP32 at
+    1e-5 and in FP64 at 1e-12 against the oracle."""
+    _window_parity("T", None, warm=200, precision=precision, events=True)

@@ -55,9 +55,9 @@ def test_overlapping_spheres_share_nodes_like_the_oracle(where):
         assert e.pop("owner_equal"), f"maps differ at t={h}"
         e.pop("df")
         for k, val in e.items():
-            assert val <= 1e-11, (h, k, val)
+            assert val <= 1e-12, (h, k, val)
         ep = compare_particles(o, lat)
-        assert ep["x"] < 1e-11 and ep["v"] < 1e-11 and ep["w"] < 1e-11
+        assert ep["x"] < 1e-12 and ep["v"] < 1e-12 and ep["w"] < 1e-12
         for k in ("Fliq", "Tliq", "Fd", "Td", "Fc", "Tc", "FSC", "TSC"):
             assert ep[k] < 1e-12, (h, k, ep[k])
         rec = o.particles()
@@ -118,9 +118,9 @@ def test_sphere_wider_than_the_box_is_listed_once():
         assert e.pop("owner_equal")
         e.pop("df")
         for k, val in e.items():
-            assert val <= 1e-11, (h, k, val)
+            assert val <= 1e-12, (h, k, val)
         ep = compare_particles(o, lat)
-        assert ep["x"] < 1e-11 and ep["v"] < 1e-11
+        assert ep["x"] < 1e-12 and ep["v"] < 1e-12
         for k in ("Fliq", "Tliq", "Fd", "Td", "Fc", "Tc", "FSC", "TSC"):
             assert ep[k] < 1e-12, (h, k, ep[k])
     assert (o.owner() == 0).sum() > 0 and (o.owner() == 1).sum() > 0

@@ -65,10 +65,10 @@ def test_pair_forces_over_many_cells():
         assert e.pop("owner_equal"), f"maps differ at t={h}"
         e.pop("df")
         for k, val in e.items():
-            assert val <= 1e-11, (h, k, val)
-        assert ep["x"] < 1e-11 and ep["v"] < 1e-11 and ep["w"] < 1e-11
+            assert val <= 1e-12, (h, k, val)
+        assert ep["x"] < 1e-12 and ep["v"] < 1e-12 and ep["w"] < 1e-12
         for k in ("FH", "Fliq", "Tliq", "FSC", "TSC", "Fd", "Td", "Fc", "Tc"):
-            assert ep[k] < 1e-11, (h, k, ep[k])
+            assert ep[k] < 1e-12, (h, k, ep[k])
     # every pair is in contact: the Hertz force acts on every sphere
     fh = np.linalg.norm(o.particles()[:, O.REC["FH"]:O.REC["FH"] + 3], axis=1)
     assert (fh > 0).all(), int((fh == 0).sum())

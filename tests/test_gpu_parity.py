@@ -126,10 +126,10 @@ def test_moving_spheres_fp64(walls):
         lat.step(h - done)
         events += int((own0 != o.owner()).sum())
         done = h
-        _check(o, lat, 1e-11, f"spheres t={h}", df_gate=h <= 10)
+        _check(o, lat, TOL64, f"spheres t={h}", df_gate=h <= 10)
         ep = compare_particles(o, lat)
         print("particles", {k: f"{v:.1e}" for k, v in ep.items()}, flush=True)
-        assert ep["x"] < 1e-11 and ep["v"] < 1e-11 and ep["w"] < 1e-11 and ep["q"] < 1e-12
+        assert ep["x"] < 1e-12 and ep["v"] < TOL64 and ep["w"] < TOL64 and ep["q"] < TOL64
         for k in ("Fliq", "Tliq", "Fd", "Td", "Fc", "Tc", "FH", "FSC", "TSC"):
             assert ep[k] < 1e-12, k
     assert events > 0
@@ -173,10 +173,10 @@ def test_one_component_moving_spheres_fp64(walls):
         lat.step(h - done)
         events += int((own0 != o.owner()).sum())
         done = h
-        _check(o, lat, 1e-11, f"one-component spheres t={h}", df_gate=h <= 10)
+        _check(o, lat, TOL64, f"one-component spheres t={h}", df_gate=h <= 10)
         ep = compare_particles(o, lat)
         print("particles", {k: f"{v:.1e}" for k, v in ep.items()}, flush=True)
-        assert ep["x"] < 1e-11 and ep["v"] < 1e-11 and ep["w"] < 1e-11
+        assert ep["x"] < 1e-12 and ep["v"] < TOL64 and ep["w"] < TOL64
         for k in ("Fliq", "Tliq", "Fd", "Td", "Fc", "Tc", "FH"):
             assert ep[k] < 1e-12, k
     assert events > 0

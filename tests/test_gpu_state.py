@@ -75,3 +75,60 @@ def test_snapshot_mismatch_and_nonfinite():
     obs = a.observables(raise_on_flag=False)
     assert obs.flags & 2
     a.close()
+
+
+def test_set_particles_checks_and_moves_only_before_the_first_step():
+    """lb_set_particles: every value must be finite and q non-zero; before the
+    first step positions may change (wrapped into the box, checked for overlap
+    like lb_add_particles, map rasterised again); after it only v, w, q and
+    the previous forces may, and a moved sphere is refused. A refused call
+    leaves the state as it was."""
+    from paper_2004_04080_amd import Lattice, LBError
+    from paper_2004_04080_amd import binding as B
+    w = synth.Workload("setp", 40, 36, 32, seed=synth.BASE_SEED + 53)
+    lat = Lattice(_params("fp64"), w.densities())
+    lat.add_particles(np.array([[10.0, 10.0, 10.0], [30.0, 20.0, 16.0], [20.0, 28.0, 24.0]]))
+    rec = lat.particles()
+    own0 = lat.owner()
+
+    bad = rec.copy()
+    bad[0, B.REC["v"]] = np.nan
+    with pytest.raises(LBError) as e:
+        lat.set_particles(bad)
+    assert e.value.status == B.LB_E_ARG
+    bad = rec.copy()
+    bad[1, B.REC["q"]:B.REC["q"] + 4] = 0.0
+    with pytest.raises(LBError):
+        lat.set_particles(bad)
+    bad = rec.copy()
+    bad[1, 0:3] = bad[0, 0:3] + np.array([5.0, 0.0, 0.0])      # centres 5 < 2R apart
+    with pytest.raises(LBError) as e:
+        lat.set_particles(bad)
+    assert e.value.status == B.LB_E_OVERLAP
+    assert np.array_equal(lat.owner(), own0)
+    np.testing.assert_array_equal(lat.particles(), rec)
+
+    # before the first step: a move, with a coordinate just below zero
+    moved = rec.copy()
+    moved[0, 0] = -1e-17          # wraps to x = 0, not to x = 40
+    lat.set_particles(moved)
+    got = lat.particles()
+    assert got[0, 0] == 0.0
+    assert not np.array_equal(lat.owner(), own0)
+    lat.step(2)
+
+    # after the first step: velocities may change, positions may not
+    rec = lat.particles()
+    faster = rec.copy()
+    faster[:, B.REC["v"]:B.REC["v"] + 3] += 0.001
+    lat.set_particles(faster)
+    np.testing.assert_array_equal(lat.particles()[:, B.REC["v"]:B.REC["v"] + 3],
+                                  faster[:, B.REC["v"]:B.REC["v"] + 3])
+    moved = lat.particles()
+    moved[0, 0] += 0.25
+    with pytest.raises(LBError) as e:
+        lat.set_particles(moved)
+    assert e.value.status == B.LB_E_STATE
+    lat.step(1)
+    assert lat.observables().flags == 0
+    lat.close()
