@@ -225,6 +225,24 @@ int lb_step(struct lb_ctx* ctx, int32_t nsteps);
  * overflow) when flagged (out is still filled). */
 int lb_observables(struct lb_ctx* ctx, lb_obs* out);
 
+/* lb_observables for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same outputs and errors, computed by the same kernels, with the
+ * reduction partials and the sphere sums in a static device array of the
+ * library (at most 1024 partial records of 16 doubles, its final record and
+ * 8 sphere sums: about 131 KB, held on each device the library runs on until
+ * the process ends) instead of the context's work buffer. It calls no
+ * hipMalloc, hipFree or other allocating routine and allocates no host heap
+ * memory. Every call on a device shares that device's array: calls that
+ * overlap in time on one device (two streams, two threads) race and must not
+ * be made. Errors as lb_observables, plus LB_E_CAPACITY if a reduction would
+ * need more than the array holds (no box the library accepts does) and
+ * LB_E_STATE if the array's address could not be taken at lb_init. The
+ * sphere sums are added in another order than lb_observables adds them (a
+ * fixed tree instead of a compensated serial sum), so they may differ in the
+ * last bits. Synchronises. */
+int lb_observables_noalloc(struct lb_ctx* ctx, lb_obs* out);
+
 /* Moments of the current state on fluid nodes (0 on solid nodes), host FP64:
  * rho [ncomp][N] and mixture velocity u [N][3] (Eq. scvel; NULL to skip). Synchronises. */
 int lb_get_fields(struct lb_ctx* ctx, double* rho, double* u);

@@ -28,7 +28,7 @@ EXPORTED = [
     "lb_get_populations", "lb_set_populations", "lb_get_owner", "lb_get_particles",
     "lb_set_particles", "lb_num_particles", "lb_loss", "lb_backward", "lb_sync", "lb_free",
     "lb_timing", "lb_timing_read", "lb_state_bytes", "lb_get_state", "lb_set_state",
-    "lb_domain_workspace", "lb_domain_size",
+    "lb_domain_workspace", "lb_domain_size", "lb_observables_noalloc",
 ]
 NPHASE = 5
 PHASES = ("density", "spheres", "fill", "collide", "integrate")
@@ -109,6 +109,7 @@ def lib():
     L.lb_add_particles.argtypes = [vp, C.c_int32, dp, dp, dp, dp]
     L.lb_step.argtypes = [vp, C.c_int32]
     L.lb_observables.argtypes = [vp, C.POINTER(lb_obs)]
+    L.lb_observables_noalloc.argtypes = [vp, C.POINTER(lb_obs)]
     L.lb_get_fields.argtypes = [vp, dp, dp]
     L.lb_get_psi.argtypes = [vp, dp]
     L.lb_get_populations.argtypes = [vp, dp]

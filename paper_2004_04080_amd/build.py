@@ -33,7 +33,8 @@ FLAGS = [
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = ["lb_fluid.hip", "lb_particles.hip", "lb_adjoint.hip", "lb_domain.hip", "lb_api.hip"]
+SOURCES = ["lb_fluid.hip", "lb_particles.hip", "lb_adjoint.hip", "lb_domain.hip", "lb_api.hip",
+           "lb_noalloc.hip"]
 LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 
 

@@ -358,6 +358,11 @@ int lb_init(const lb_params* p, const lb_buffers* b, const double* rho0, const d
   c->wl = wl;
   c->al = al;
   c->has_solids = has_solids(*p);
+  if (noalloc_setup(c) != LB_OK) {
+    g_last_error = c->err;
+    delete c;
+    return LB_E_HIP;
+  }
   for (int d = 0; d < 3; ++d) c->ncell[d] = nc[d];
   const double R = p->radius;
   c->mass = p->particle_density * 4.0 / 3.0 * M_PI * R * R * R;
@@ -684,16 +689,54 @@ int lb_sync(lb_ctx* c) {
   return LB_OK;
 }
 
+}  // extern "C"
+
+namespace lbh {
+
 // Pseudo-potential of the current state on its map: moments, then the
 // virtual densities of the frontier (the sphere fill leaves the force
 // accumulators alone).
 int current_psi(lb_ctx* c) {
   HIPCHK(c, launch_density(c, c->B.f[c->cur]));
-  const uint16_t* own = owner_now(c);
+  const uint16_t* own = c->has_solids ? static_cast<const uint16_t*>(c->B.owner[c->own_old])
+                                      : nullptr;
   if (c->nparticles > 0) HIPCHK(c, launch_fill_particles(c, own, false));
   if (c->P.walls) HIPCHK(c, launch_fill_walls(c, own));
   return LB_OK;
 }
+
+// The fluid part of lb_obs from the reduction results r (layout of
+// k_reduce_partials), after clearing the whole record.
+void obs_fluid(const lb_ctx* c, const double* r, lb_obs* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->step = c->step;
+  o->fluid_nodes = int64_t(r[10]);
+  for (int k = 0; k < c->geo.ncomp; ++k) {
+    o->mass[k] = r[10] * c->P.rho0[k] + r[k];
+    o->rho_min[k] = c->P.rho0[k] + r[5 + k];
+    o->rho_max[k] = c->P.rho0[k] + r[7 + k];
+  }
+  for (int d = 0; d < 3; ++d) {
+    o->momentum[d] = r[2 + d];
+    o->phys_momentum[d] = r[2 + d] + 0.5 * r[12 + d];
+  }
+  o->u_max = r[9];
+  o->nparticles = c->nparticles;
+}
+
+// The flags of lb_obs (work-buffer flags and the non-finite count of r) and
+// the status they make lb_observables return.
+int obs_flags(lb_ctx* c, const double* r, const int32_t* flags, lb_obs* o) {
+  o->flags = (flags[0] ? 1 : 0) | (r[11] > 0 || !std::isfinite(r[0]) ? 2 : 0) | (flags[2] ? 4 : 0);
+  if (o->flags & 1) return fail(c, LB_E_PARTICLE_SPEED, "sphere speed exceeded 1/2 per step");
+  if (o->flags & 2) return fail(c, LB_E_NONFINITE, "non-finite populations");
+  if (o->flags & 4) return fail(c, LB_E_CAPACITY, "frontier list overflow");
+  return LB_OK;
+}
+
+}  // namespace lbh
+
+extern "C" {
 
 int lb_observables(lb_ctx* c, lb_obs* o) {
   if (!c || !o) return LB_E_ARG;
@@ -701,7 +744,7 @@ int lb_observables(lb_ctx* c, lb_obs* o) {
   // the force density of the physical momentum needs the pseudo-potential
   const int rc = current_psi(c);
   if (rc != LB_OK) return rc;
-  HIPCHK(c, launch_reduce(c, red));
+  HIPCHK(c, launch_reduce(c, reinterpret_cast<double*>(wptr(c, c->wl.partials)), red));
   double r[RED_N];
   int32_t flags[3];
   HIPCHK(c, hipMemcpyAsync(r, red, sizeof(r), hipMemcpyDeviceToHost, c->stream));
@@ -715,17 +758,7 @@ int lb_observables(lb_ctx* c, lb_obs* o) {
                              hipMemcpyDeviceToHost, c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  std::memset(o, 0, sizeof(*o));
-  o->step = c->step;
-  o->fluid_nodes = int64_t(r[10]);
-  for (int k = 0; k < c->geo.ncomp; ++k) {
-    o->mass[k] = r[10] * c->P.rho0[k] + r[k];
-    o->rho_min[k] = c->P.rho0[k] + r[5 + k];
-    o->rho_max[k] = c->P.rho0[k] + r[7 + k];
-  }
-  for (int d = 0; d < 3; ++d) o->momentum[d] = r[2 + d];
-  o->u_max = r[9];
-  o->nparticles = c->nparticles;
+  obs_fluid(c, r, o);
   // particle sums with Neumaier compensation
   auto nsum = [&](auto get) {
     double s = 0, comp = 0;
@@ -745,7 +778,6 @@ int lb_observables(lb_ctx* c, lb_obs* o) {
   o->particle_ke_rot = nsum([&](const double* P) {
     return 0.5 * c->inertia * (P[PS_W] * P[PS_W] + P[PS_W + 1] * P[PS_W + 1] + P[PS_W + 2] * P[PS_W + 2]);
   });
-  for (int d = 0; d < 3; ++d) o->phys_momentum[d] = r[2 + d] + 0.5 * r[12 + d];
   {
     double s = 0, comp = 0;
     for (int p = 0; p < c->nparticles; ++p) {
@@ -756,11 +788,7 @@ int lb_observables(lb_ctx* c, lb_obs* o) {
     }
     o->flink_abs = s + comp;
   }
-  o->flags = (flags[0] ? 1 : 0) | (r[11] > 0 || !std::isfinite(r[0]) ? 2 : 0) | (flags[2] ? 4 : 0);
-  if (o->flags & 1) return fail(c, LB_E_PARTICLE_SPEED, "sphere speed exceeded 1/2 per step");
-  if (o->flags & 2) return fail(c, LB_E_NONFINITE, "non-finite populations");
-  if (o->flags & 4) return fail(c, LB_E_CAPACITY, "frontier list overflow");
-  return LB_OK;
+  return obs_flags(c, r, flags, o);
 }
 
 int lb_get_fields(lb_ctx* c, double* rho, double* u) {

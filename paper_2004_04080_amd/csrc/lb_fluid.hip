@@ -1076,12 +1076,13 @@ hipError_t launch_owner_to_int(lb_ctx* c, const uint16_t* owner, uint32_t first,
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(lb_ctx* c, double* out_dev) {
+int reduce_blocks(const lb_ctx* c) { return int(std::min<uint64_t>(RED_BLOCKS, nblocks(c->geo.N))); }
+
+hipError_t launch_reduce(lb_ctx* c, double* partial, double* out_dev) {
   const auto& g = c->geo;
   const auto& P = c->P;
   const int kb = g.ncomp == 2 ? 1 : 0;
-  double* partial = reinterpret_cast<double*>(wptr(c, c->wl.partials));
-  const int nb = int(std::min<uint64_t>(RED_BLOCKS, nblocks(g.N)));
+  const int nb = reduce_blocks(c);
   const double Gs = P.G * P.sc_norm;
   if (fp64(c))
     hipLaunchKernelGGL(k_reduce_partials<double>, dim3(nb), dim3(BLOCK), 0, c->stream,

@@ -91,6 +91,8 @@ struct lb_ctx {
   double phase_ms[LB_NPHASE] = {};
   int64_t phase_n[LB_NPHASE] = {};
   std::string err;
+  // static scratch of lb_observables_noalloc on the context's device
+  void* noalloc_scratch = nullptr;
 };
 
 namespace lbh {
@@ -116,7 +118,19 @@ hipError_t launch_set_populations(lb_ctx* c, int k, int i, uint32_t first, uint3
                                   const double* in);
 hipError_t launch_get_fields(lb_ctx* c, uint32_t first, uint32_t count, double* out);
 hipError_t launch_get_psi(lb_ctx* c, uint32_t first, uint32_t count, int comp, double* out);
-hipError_t launch_reduce(lb_ctx* c, double* out_dev);
+// observables of the current state: reduce_blocks(c) partial records of RED_N
+// doubles into `partial`, the final RED_N doubles into out_dev
+int reduce_blocks(const lb_ctx* c);
+hipError_t launch_reduce(lb_ctx* c, double* partial, double* out_dev);
+// pseudo-potential of the current state on its map (moments and fills)
+int current_psi(lb_ctx* c);
+// lb_obs from the reduction results: the fluid part (clears the record first),
+// then the flags and the status they make the call return
+void obs_fluid(const lb_ctx* c, const double* r, lb_obs* o);
+int obs_flags(lb_ctx* c, const double* r, const int32_t* flags, lb_obs* o);
+// device address of the static scratch of the allocation-free entry point
+// on the current device, taken once per device (LB_OK or LB_E_HIP)
+int noalloc_setup(lb_ctx* c);
 hipError_t launch_owner_to_int(lb_ctx* c, const uint16_t* owner, uint32_t first,
                                uint32_t count, int32_t* out);
 

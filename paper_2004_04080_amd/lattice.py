@@ -224,12 +224,15 @@ class Lattice:
         return {name: (ms[i], n[i]) for i, name in enumerate(B.PHASES)}
 
     # -- queries ---------------------------------------------------------------
-    def observables(self, raise_on_flag: bool = True) -> Observables:
+    def observables(self, raise_on_flag: bool = True, noalloc: bool = False) -> Observables:
+        """lb_observables, or with noalloc=True lb_observables_noalloc (the
+        reduction scratch in the library's static device array)."""
         o = B.lb_obs()
-        rc = B.lib().lb_observables(self._ctx, C.byref(o))
+        name = "lb_observables_noalloc" if noalloc else "lb_observables"
+        rc = getattr(B.lib(), name)(self._ctx, C.byref(o))
         if rc not in (B.LB_OK, B.LB_E_PARTICLE_SPEED, B.LB_E_NONFINITE) or (
                 raise_on_flag and rc != B.LB_OK):
-            self._chk(rc, "lb_observables")
+            self._chk(rc, name)
         return Observables(o.step, o.fluid_nodes, np.array(o.mass[:]), np.array(o.momentum[:]),
                            np.array(o.rho_min[:]), np.array(o.rho_max[:]), o.u_max,
                            np.array(o.particle_momentum[:]), o.particle_ke, o.particle_ke_rot,
