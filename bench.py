@@ -6,9 +6,14 @@ G = 0.65, rho_k = 1 + 0.01 (2U - 1) per node) and 32,000 moving spheres of
 radius 5.5 placed at random without overlap (16.6% solids), FP32 deviation
 storage. Inputs are seeded and synthetic (no dataset is involved).
 
-Prints one JSON line: MLUPS (all nodes counted, paper's Eq. glups), the
-roofline of the dominant kernel (collide-stream-bounce-back) from its own
-HIP-event time, the FP64 path's MLUPS on the same workload, and the serial
+Prints one JSON line: MLUPS (all nodes counted, paper's Eq. glups) of --steps
+steps after --warmup steps, timed with HIP events and no per-phase events;
+then a second pass of --steps steps with per-phase HIP events gives the
+kernel split and the roofline of the dominant kernel (collide-stream-
+bounce-back). The line also carries the same workload timed from step 1000,
+the FP64 path (MLUPS, roofline, FP32 error against it), the adjoint leg, the
+fluid-only and confined boxes, the streaming probes of the library (the
+attainable read, write, copy and collide-pattern rates) and the serial
 oracle's MLUPS on a bounded sample of the workload (CPU baseline).
 """
 from __future__ import annotations
@@ -58,7 +63,26 @@ def link_count(owner: np.ndarray, shape) -> tuple:
     return int(np.count_nonzero(fluid)), links
 
 
-def run_gpu(w, rho, x, precision, steps, warmup, want_roofline, want_fields=False):
+def _timed(lat, steps):
+    """Milliseconds of `steps` steps between HIP events on the library's stream."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def run_gpu(w, rho, x, precision, steps, warmup, want_roofline, want_fields=False,
+            late_at=0, fields_at=None):
+    """One run of workload w: `warmup` untimed steps, `steps` timed steps
+    (the headline, without per-phase events), then `steps` more with per-phase
+    HIP events (the kernel split and the roofline). With fields_at the run
+    then steps on to that step and reads the fields; with late_at it steps on
+    to that step and times `steps` clean steps once more."""
     import torch
     from paper_2004_04080_amd import Lattice
     t0 = time.time()
@@ -69,36 +93,50 @@ def run_gpu(w, rho, x, precision, steps, warmup, want_roofline, want_fields=Fals
     lat.step(warmup)
     lat.sync()
     log(f"[bench] {w.name} {precision}: {warmup} warm-up steps done")
+    ms = _timed(lat, steps) if steps else 0.0
     lat.timing(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(lat.stream)
-    lat.step(steps)
-    e1.record(lat.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms_ph = _timed(lat, steps)
     phases = lat.timing_read()
     lat.timing(False)
+    done = warmup + 2 * steps
     obs = lat.observables(raise_on_flag=False)
-    log(f"[bench] {w.name} {precision}: {steps} steps in {ms:.1f} ms; phases {phases}")
-    out = dict(ms_per_step=ms / steps, mlups=w.N * steps / (ms * 1e-3) / 1e6, phases=phases,
-               flags=obs.flags, mass=obs.mass.tolist())
+    if not steps:
+        ms = ms_ph
+    log(f"[bench] {w.name} {precision}: {steps} steps in {ms:.1f} ms; with phase events "
+        f"{ms_ph:.1f} ms; phases {phases}")
+    out = dict(ms_per_step=ms / max(steps, 1), mlups=w.N * steps / (ms * 1e-3) / 1e6 if steps else 0,
+               ms_per_step_phase_pass=ms_ph / max(steps, 1), phases=phases, flags=obs.flags,
+               mass=obs.mass.tolist())
     if want_roofline:
         lat.domain_size()          # the first call creates the FFT plan
         t = time.time()
         L, _ = lat.domain_size()
         out["domain_size"] = {"L": round(L, 4), "ms": round((time.time() - t) * 1e3, 2)}
-    if want_roofline or want_fields:
         own = lat.owner()
-        if want_roofline:
-            nfl, nlinks = link_count(own, (w.nx, w.ny, w.nz))
-            out["fluid_nodes"] = nfl
-            out["links"] = nlinks
-        if want_fields:
-            rho_f, u_f = lat.fields()
-            out["fields"] = (own == 0, rho_f, u_f)
+        nfl, nlinks = link_count(own, (w.nx, w.ny, w.nz))
+        out["fluid_nodes"] = nfl
+        out["links"] = nlinks
         del own
+    if fields_at is not None:
+        if fields_at > done:
+            lat.step(fields_at - done)
+            done = fields_at
+        own = lat.owner()
+        rho_f, u_f = lat.fields()
+        out["fields"] = (own == 0, rho_f, u_f)
+        out["fields_step"] = done
+        del own
+    if late_at:
+        lat.step(max(late_at - done, 0))
+        done = max(late_at, done)
+        lat.sync()
+        ms_late = _timed(lat, steps)
+        obs = lat.observables(raise_on_flag=False)
+        out["late"] = {"from_step": done, "steps": steps,
+                       "ms_per_step": round(ms_late / steps, 4),
+                       "value": round(w.N * steps / (ms_late * 1e-3) / 1e6, 1), "unit": "MLUPS",
+                       "flags": obs.flags}
+        log(f"[bench] {w.name} {precision}: from step {done}, {steps} steps in {ms_late:.1f} ms")
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -273,6 +311,58 @@ def copy_probe(gib: float, reps: int = 5) -> dict:
             "GBps_read_plus_write": round(2 * n / (ms * 1e-3) / 1e9, 1)}
 
 
+def stream_probes(gib: float = 8.0, box=(512, 512, 512), reps: int = 10) -> dict:
+    """The library's streaming probes (lb_probe_stream): hand-written read,
+    write and copy kernels over `gib` GiB, and the fused step's access pattern
+    (2 x 19 FP32 planes gathered with the D3Q19 pull offsets and stored in
+    place) on a box of the bench's size. GB/s counts the bytes each kernel
+    must move (read + written)."""
+    import ctypes as C
+    import torch
+    from paper_2004_04080_amd import binding as B
+    lib = B.lib()
+    stream = torch.cuda.current_stream()
+    out = {}
+    n = int(gib * (1 << 30)) // 16 * 16
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros_like(a)
+    for kind, name, moved in ((0, "read", n), (1, "write", n), (2, "copy", 2 * n)):
+        ms = C.c_double()
+        B.check(lib.lb_probe_stream(kind, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), n,
+                                    0, 0, 0, reps, C.c_void_p(stream.cuda_stream), C.byref(ms)),
+                "lb_probe_stream")
+        out[name] = {"GBps": round(moved / (ms.value * 1e-3) / 1e9, 1), "bytes": moved,
+                     "ms": round(ms.value, 4)}
+    del a, b
+    torch.cuda.empty_cache()
+    N = box[0] * box[1] * box[2]
+    nb = 2 * 19 * N * 4
+    a = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros_like(a)
+    ms = C.c_double()
+    B.check(lib.lb_probe_stream(3, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), nb,
+                                box[0], box[1], box[2], reps, C.c_void_p(stream.cuda_stream),
+                                C.byref(ms)), "lb_probe_stream")
+    out["collide_pattern"] = {"GBps": round(2 * nb / (ms.value * 1e-3) / 1e9, 1),
+                              "bytes": 2 * nb, "ms": round(ms.value, 4),
+                              "box": f"{box[0]}x{box[1]}x{box[2]}"}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def other_line(wo, ro, es, precision, steps):
+    rl = roofline(wo, ro, es, precision)
+    return {"workload": f"{wo.name}: {wo.nx}x{wo.ny}x{wo.nz}, {wo.nparticles} spheres"
+                        + (", walls" if wo.walls else ""),
+            "precision": precision,
+            "value": round(ro["mlups"], 1), "unit": "MLUPS",
+            "ms_per_step": round(ro["ms_per_step"], 4),
+            "collide_GBps": rl["achieved"], "collide_frac": rl["frac"],
+            "phases_ms_per_step": {k: round(v[0] / max(steps, 1), 4)
+                                   for k, v in ro["phases"].items()}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,13 +371,16 @@ def main():
     ap.add_argument("--workload", default="T")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--late", type=int, default=1000,
+                    help="also time --steps steps of the main workload from this step (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 run (and with it the FP32 accuracy figure)")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--workloads", default="",
+    ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--workloads", default="MT0,C4",
                     help="comma-separated further boxes (C2,C3,C4,MT0) timed after the main "
-                         "one and reported under other_workloads (FP32, same step counts)")
+                         "one and reported under other_workloads (same step counts)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB and report it")
     ap.add_argument("--coarsening", type=int, default=0,
@@ -314,35 +407,38 @@ def main():
     x = w.centres()
     log(f"[bench] {w.name}: seeded inputs ready in {time.time() - t0:.1f}s")
     check = not args.no_fp64 and args.precision == "fp32"
+    cmp_at = args.warmup + 2 * args.steps
     res = run_gpu(w, rho, x, args.precision, args.steps, args.warmup, want_roofline=True,
-                  want_fields=check)
+                  fields_at=cmp_at if check else None, late_at=args.late)
     fp64 = acc = None
     if check:
-        # the FP64 run ends at the same step as the FP32 run, so both can be compared
-        total = args.warmup + args.steps
-        fsteps = min(args.fp64_steps, total)
-        r64 = run_gpu(w, rho, x, "fp64", fsteps, total - fsteps, want_roofline=False,
-                      want_fields=True)
+        # the FP64 run: its phase pass ends at the step where the FP32 fields were read
+        fsteps = max(1, min(args.fp64_steps, cmp_at // 2))
+        r64 = run_gpu(w, rho, x, "fp64", fsteps, cmp_at - 2 * fsteps, want_roofline=True,
+                      fields_at=cmp_at)
         fp64 = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "steps": fsteps,
-                "ms_per_step": round(r64["ms_per_step"], 3)}
-        acc = accuracy(res.pop("fields"), r64.pop("fields"), total)
-        log(f"[bench] FP32 against FP64 after {total} steps: {acc}")
+                "ms_per_step": round(r64["ms_per_step"], 3),
+                "roofline": roofline(w, r64, 8, "fp64"),
+                "phases_ms_per_step": {k: round(v[0] / max(fsteps, 1), 4)
+                                       for k, v in r64["phases"].items()}}
+        acc = accuracy(res.pop("fields"), r64.pop("fields"), cmp_at)
+        log(f"[bench] FP32 against FP64 at step {cmp_at}: {acc}")
     adj = None if args.no_adjoint else adjoint_leg()
     others = []
     for name in [v for v in args.workloads.split(",") if v]:
         wo = synth.workload(name)
         ro = run_gpu(wo, wo.densities(), wo.centres(), args.precision, args.steps, args.warmup,
                      want_roofline=True)
-        rl = roofline(wo, ro, es, args.precision)
-        others.append({"workload": f"{wo.name}: {wo.nx}x{wo.ny}x{wo.nz}, {wo.nparticles} spheres"
-                                   + (", walls" if wo.walls else ""),
-                       "value": round(ro["mlups"], 1), "unit": "MLUPS",
-                       "ms_per_step": round(ro["ms_per_step"], 4),
-                       "collide_GBps": rl["achieved"], "collide_frac": rl["frac"],
-                       "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)
-                                              for k, v in ro["phases"].items()}})
+        others.append(other_line(wo, ro, es, args.precision, args.steps))
         log(f"[bench] {others[-1]}")
+    probes = None if args.no_probes else stream_probes(box=(w.nx, w.ny, w.nz))
+    if probes:
+        log(f"[bench] streaming probes: {probes}")
     cpu = None if args.no_cpu_baseline else cpu_baseline()
+    rl = roofline(w, res, es, args.precision)
+    if probes:
+        rl["frac_of_collide_pattern_probe"] = round(
+            rl["achieved"] / probes["collide_pattern"]["GBps"], 4)
     line = {
         "metric": METRIC,
         "value": round(res["mlups"], 1),
@@ -360,14 +456,17 @@ def main():
                                f"(tau=1, G=0.65) + {w.nparticles} moving spheres R={w.radius}",
                    "nodes": w.N, "spheres": w.nparticles,
                    "fluid_nodes": res["fluid_nodes"], "links": res["links"]},
-        "roofline": roofline(w, res, es, args.precision),
+        "roofline": rl,
         "cpu_baseline": cpu,
         "fp64": fp64,
         "accuracy": acc,
+        "late": res.get("late"),
         "adjoint": adj,
         "other_workloads": others or None,
-        "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)
-                               for k, v in res["phases"].items()},
+        "stream_probes": probes,
+        "phase_pass": {"ms_per_step": round(res["ms_per_step_phase_pass"], 4),
+                       "phases_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4)
+                                              for k, v in res["phases"].items()}},
         "domain_size": res.get("domain_size"),
         "flags": res["flags"],
     }

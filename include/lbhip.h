@@ -330,6 +330,21 @@ int lb_domain_workspace(struct lb_ctx* ctx, size_t* bytes, int32_t* nshell);
 int lb_domain_size(struct lb_ctx* ctx, void* work, size_t work_bytes, double* L, double* S,
                    int32_t nshell);
 
+/* Streaming probes (measurement only, not part of the step): the time of a
+ * plain bandwidth-bound kernel on this device, the ceiling against which the
+ * step's kernels are read. kind 0 reads `bytes` of src (16-byte chunks; dst,
+ * at least 1 KB, is only a sink that finite inputs never reach); kind 1
+ * writes `bytes` of dst; kind 2 copies `bytes` from src to dst; kind 3 moves
+ * two components of 19 FP32 planes of N = nx ny nz nodes in the pattern of
+ * the fused step: plane i of node n is gathered from node n - c_i (D3Q19,
+ * periodic) of src and stored at n in dst (src and dst each 2*19*N*4 bytes,
+ * bytes >= that; one plane below 4 GiB). Device pointers, 16-byte aligned,
+ * owned by the caller. One untimed launch, then reps launches on `stream`
+ * (hipStream_t) between HIP events; *ms_per_launch gets their mean.
+ * Synchronises. Errors: LB_E_ARG, LB_E_SHAPE, LB_E_HIP. */
+int lb_probe_stream(int32_t kind, const void* src, void* dst, size_t bytes, int32_t nx,
+                    int32_t ny, int32_t nz, int32_t reps, void* stream, double* ms_per_launch);
+
 /* Wait for all work queued by the context. */
 int lb_sync(struct lb_ctx* ctx);
 

@@ -28,7 +28,7 @@ EXPORTED = [
     "lb_get_populations", "lb_set_populations", "lb_get_owner", "lb_get_particles",
     "lb_set_particles", "lb_num_particles", "lb_loss", "lb_backward", "lb_sync", "lb_free",
     "lb_timing", "lb_timing_read", "lb_state_bytes", "lb_get_state", "lb_set_state",
-    "lb_domain_workspace", "lb_domain_size", "lb_observables_noalloc",
+    "lb_domain_workspace", "lb_domain_size", "lb_observables_noalloc", "lb_probe_stream",
 ]
 NPHASE = 5
 PHASES = ("density", "spheres", "fill", "collide", "integrate")
@@ -130,6 +130,8 @@ def lib():
     L.lb_set_state.argtypes = [vp, vp, C.c_size_t]
     L.lb_domain_workspace.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int32)]
     L.lb_domain_size.argtypes = [vp, vp, C.c_size_t, dp, dp, C.c_int32]
+    L.lb_probe_stream.argtypes = [C.c_int32, vp, vp, C.c_size_t, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_int32, vp, dp]
     _lib = L
     return L
 

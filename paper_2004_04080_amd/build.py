@@ -34,7 +34,7 @@ FLAGS = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 SOURCES = ["lb_fluid.hip", "lb_particles.hip", "lb_adjoint.hip", "lb_domain.hip", "lb_api.hip",
-           "lb_noalloc.hip"]
+           "lb_noalloc.hip", "lb_probe.hip"]
 LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 
 

@@ -151,3 +151,21 @@ def test_null_context_calls_fail_cleanly():
     assert L.lb_observables(None, C.byref(o)) == B.LB_E_ARG
     L.lb_free(None)
     assert B.strerror(B.LB_E_PARTICLE_SPEED)
+
+
+def test_stream_probe_rejects_bad_arguments_on_the_host():
+    """lb_probe_stream checks its arguments before any device call."""
+    import ctypes as C
+    from paper_2004_04080_amd import binding as B
+    lib = B.lib()
+    ms = C.c_double()
+    buf = C.c_void_p(16)       # never dereferenced: every call below is refused first
+    assert lib.lb_probe_stream(7, buf, buf, 1024, 0, 0, 0, 1, None, C.byref(ms)) == B.LB_E_ARG
+    assert lib.lb_probe_stream(2, buf, buf, 1024, 0, 0, 0, 0, None, C.byref(ms)) == B.LB_E_ARG
+    assert lib.lb_probe_stream(2, buf, buf, 1024, 0, 0, 0, 1, None, None) == B.LB_E_ARG
+    assert lib.lb_probe_stream(1, None, None, 1024, 0, 0, 0, 1, None, C.byref(ms)) == B.LB_E_ARG
+    # the collide pattern: a plane above 4 GiB, and buffers smaller than 2 x 19 planes
+    assert lib.lb_probe_stream(3, buf, buf, 1 << 40, 2048, 1024, 1024, 1, None,
+                               C.byref(ms)) == B.LB_E_SHAPE
+    assert lib.lb_probe_stream(3, buf, buf, 38 * 4 * 64 - 4, 4, 4, 4, 1, None,
+                               C.byref(ms)) == B.LB_E_SHAPE
