@@ -265,13 +265,21 @@ def adjoint_leg():
             "rel_err": float(f"{abs(dG - fd) / abs(fd):.3e}")}
 
 
-def coarsening(name: str, steps: int, every: int) -> dict:
-    """Average domain size L(t) (Eq. Cluster_L_eq) along one FP32 run of a
-    synthetic box, with the wall-clock rate of the run."""
+def coarsening(name: str, steps: int, every: int, precision: str = "fp32",
+               janus: bool = False) -> dict:
+    """Average domain size L(t) (Eq. Cluster_L_eq) along one run of a
+    synthetic box, with the wall-clock rate of the run. With janus the spheres
+    carry the benchmark's particle model: Janus wetting (108 +- 5 degrees,
+    constants 0.1) and lubrication (0.1, 0.67, 0.5)."""
+    import dataclasses
     import synth
     from paper_2004_04080_amd import Lattice
     w = synth.workload(name)
-    lat = Lattice(params_for(w, "fp32"), w.densities())
+    p = params_for(w, precision)
+    if janus:
+        p = dataclasses.replace(p, janus=True, janus_theta0=108.0, janus_width=10.0,
+                                janus_zeta=(0.1, 0.1), lub_mu=0.1, lub_hn=0.67, lub_hcap=0.5)
+    lat = Lattice(p, w.densities())
     if w.nparticles:
         lat.add_particles(w.centres())
     series, t0, done = [], time.time(), 0
@@ -281,13 +289,15 @@ def coarsening(name: str, steps: int, every: int) -> dict:
         done += n
         L, _ = lat.domain_size()
         series.append([done, round(L, 3)])
-        log(f"[coarsening] {w.name} step {done}: L = {L:.3f}")
+        log(f"[coarsening] {w.name} {precision}{' janus' if janus else ''} step {done}: L = {L:.3f}")
     dt = time.time() - t0
     obs = lat.observables(raise_on_flag=False)
     lat.close()
     return {"coarsening": series, "workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz}, "
-            f"{w.nparticles} spheres R={w.radius} ({100 * synth.sphere_fraction(w):.1f}% solid)",
-            "steps": steps, "seconds": round(dt, 1), "flags": obs.flags}
+            f"{w.nparticles} spheres R={w.radius} ({100 * synth.sphere_fraction(w):.1f}% solid)"
+            + (", Janus wetting 108+-5 deg (0.1, 0.1) and lubrication" if janus else
+               ", neutral wetting"),
+            "precision": precision, "steps": steps, "seconds": round(dt, 1), "flags": obs.flags}
 
 
 def copy_probe(gib: float, reps: int = 5) -> dict:
@@ -387,9 +397,12 @@ def main():
                     help="only run this many steps of --workload (FP32) and report the "
                          "average domain size every --every steps")
     ap.add_argument("--every", type=int, default=1000)
+    ap.add_argument("--janus", action="store_true",
+                    help="coarsening with the benchmark's Janus wetting and lubrication")
     args = ap.parse_args()
     if args.coarsening > 0:
-        print(json.dumps(coarsening(args.workload, args.coarsening, args.every)), flush=True)
+        print(json.dumps(coarsening(args.workload, args.coarsening, args.every, args.precision,
+                                    args.janus)), flush=True)
         return
     if args.copy_probe > 0:
         print(json.dumps(copy_probe(args.copy_probe)), flush=True)
