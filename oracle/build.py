@@ -11,14 +11,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liblbo.so")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", LIB + ".tmp", os.path.join(HERE, "lbo.cpp")]
+# AddressSanitizer and UndefinedBehaviorSanitizer, every UB report fatal; the
+# library is then loaded into a process that preloads the runtimes
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose: bool = False, out: str = LIB, sanitize: bool = False) -> str:
+    flags = SANITIZE if sanitize else ["-O2"]
+    cmd = ["g++", *flags, "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", out + ".tmp", os.path.join(HERE, "lbo.cpp")]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

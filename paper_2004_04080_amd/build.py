@@ -59,9 +59,17 @@ def _check_no_packed_fp32(src: str) -> None:
         raise RuntimeError(f"{src}: packed FP32 instructions in the device code: {found}")
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+# host code only (the device passes are never sanitised): AddressSanitizer and
+# UndefinedBehaviorSanitizer with every UB report fatal, for the CPU tests of
+# the host runtime; the process that loads such a build preloads the runtime
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def _compile(src: str, verbose: bool, obj_dir: str = OBJ_DIR, extra=()) -> str:
+    obj = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -72,19 +80,24 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
-    os.makedirs(OBJ_DIR, exist_ok=True)
+def build(verbose: bool = False, out: str = LIB, sanitize: bool = False) -> str:
+    """Build the library to `out`; with sanitize the host code carries ASan and
+    UBSan (objects in a directory of their own, no device-assembly check)."""
+    obj_dir = OBJ_DIR + ("-san" if sanitize else "")
+    extra = SANITIZE_HOST if sanitize else ()
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    os.makedirs(obj_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-        list(ex.map(_check_no_packed_fp32, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, obj_dir, extra), SOURCES))
+        if not sanitize:
+            list(ex.map(_check_no_packed_fp32, SOURCES))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, *LIBS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
