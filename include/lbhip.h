@@ -345,6 +345,16 @@ int lb_domain_size(struct lb_ctx* ctx, void* work, size_t work_bytes, double* L,
 int lb_probe_stream(int32_t kind, const void* src, void* dst, size_t bytes, int32_t nx,
                     int32_t ny, int32_t nz, int32_t reps, void* stream, double* ms_per_launch);
 
+/* Debugging the bounce-back (Sec. 3.1, steps 6 and 8: each reflected
+ * population has exactly one writer): with counts non-NULL, every later
+ * lb_step runs the collide variant that also adds 1 to counts[k][i][n]
+ * (device uint32 [ncomp][19][N], zeroed and owned by the caller) for every
+ * population it stores into slot (k, i, n) of the output buffer: the
+ * post-collision values of fluid nodes, the zeros of solid nodes and every
+ * reflection. After s steps every entry must be s. NULL switches it off.
+ * Walls or spheres required (LB_E_STATE). Slower; for tests only. */
+int lb_debug_count_writes(struct lb_ctx* ctx, void* counts);
+
 /* Wait for all work queued by the context. */
 int lb_sync(struct lb_ctx* ctx);
 

@@ -29,6 +29,7 @@ EXPORTED = [
     "lb_set_particles", "lb_num_particles", "lb_loss", "lb_backward", "lb_sync", "lb_free",
     "lb_timing", "lb_timing_read", "lb_state_bytes", "lb_get_state", "lb_set_state",
     "lb_domain_workspace", "lb_domain_size", "lb_observables_noalloc", "lb_probe_stream",
+    "lb_debug_count_writes",
 ]
 NPHASE = 5
 PHASES = ("density", "spheres", "fill", "collide", "integrate")
@@ -130,6 +131,7 @@ def lib():
     L.lb_set_state.argtypes = [vp, vp, C.c_size_t]
     L.lb_domain_workspace.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int32)]
     L.lb_domain_size.argtypes = [vp, vp, C.c_size_t, dp, dp, C.c_int32]
+    L.lb_debug_count_writes.argtypes = [vp, vp]
     L.lb_probe_stream.argtypes = [C.c_int32, vp, vp, C.c_size_t, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int32, vp, dp]
     _lib = L

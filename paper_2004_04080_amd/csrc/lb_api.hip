@@ -683,6 +683,16 @@ int lb_set_state(lb_ctx* c, const void* blob, size_t bytes) {
   return LB_OK;
 }
 
+int lb_debug_count_writes(lb_ctx* c, void* counts) {
+  if (!c) return LB_E_ARG;
+  if (counts && !c->has_solids)
+    return fail(c, LB_E_STATE, "store counting needs walls or spheres (bounce-back links)");
+  if (reinterpret_cast<uintptr_t>(counts) % 4 != 0)
+    return fail(c, LB_E_ARG, "counts must be 4-byte aligned");
+  c->write_counts = static_cast<uint32_t*>(counts);
+  return LB_OK;
+}
+
 int lb_sync(lb_ctx* c) {
   if (!c) return LB_E_ARG;
   HIPCHK(c, hipStreamSynchronize(c->stream));

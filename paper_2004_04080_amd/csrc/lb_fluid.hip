@@ -105,6 +105,7 @@ struct CollideArgs {
   uint32_t nblk;            // workgroups that hold nodes
   uint32_t band_w;          // workgroups per band and z-plane (0: whole planes)
   uint32_t plane_w;         // workgroups per z-plane
+  uint32_t* counts;         // [k][i][N] store counts of the counting variant, else null
 };
 
 // Packed direction tables for a direction index that varies per lane:
@@ -140,7 +141,7 @@ __device__ __forceinline__ int dir_opp(int i) { return i <= 8 ? ((i - 1) ^ 1) + 
 // with the face's density (pressure, equilibrium) or velocity (velocity,
 // equilibrium) and the other extrapolated: X_w = X(n) + (X(n) - X(n'))/2,
 // n' the next node inwards along z (X(n) alone if n' is solid).
-template <typename real, int NC>
+template <typename real, int NC, bool COUNT>
 __device__ void open_face(const CollideArgs& a, int face, int i, int j, uint32_t s, uint32_t x,
                           uint32_t y, uint32_t z, const real fs[NC], const real rho[NC],
                           const real u[3]) {
@@ -182,10 +183,11 @@ __device__ void open_face(const CollideArgs& a, int face, int i, int j, uint32_t
       r = wi * a.wall_rho[face][k] * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * uu);
     }
     st32(fout + (size_t(k) * Q + j) * N, s, real(r - w0));
+    if (COUNT) atomicAdd(a.counts + (size_t(k) * Q + j) * N + s, 1u);
   }
 }
 
-template <typename real, int NC>
+template <typename real, int NC, bool COUNT>
 __device__ __forceinline__ void link_one(const CollideArgs& a, int i, uint16_t o, uint32_t x,
                                          uint32_t y, uint32_t z, const real fs[NC],
                                          const real rho[NC], const real u[3], int& pid,
@@ -201,7 +203,7 @@ __device__ __forceinline__ void link_one(const CollideArgs& a, int i, uint16_t o
   if (o == OWN_WALL) {
     const bool lo = int(z) + cz == 0;
     if (a.wall_type[lo ? 0 : 1] != 0) {
-      open_face<real, NC>(a, lo ? 0 : 1, i, j, s, x, y, z, fs, rho, u);
+      open_face<real, NC, COUNT>(a, lo ? 0 : 1, i, j, s, x, y, z, fs, rho, u);
       return;
     }
     uwx = lo ? a.wall_lo[0] : a.wall_hi[0];
@@ -228,6 +230,7 @@ __device__ __forceinline__ void link_one(const CollideArgs& a, int i, uint16_t o
   for (int k = 0; k < NC; ++k) {
     const real corr = cw * rho[k];
     st32(fout + (size_t(k) * Q + j) * N, s, fs[k] - corr);
+    if (COUNT) atomicAdd(a.counts + (size_t(k) * Q + j) * N + s, 1u);
     dev += double(real(2) * fs[k] - corr);
   }
   if (p < 0 || !a.acc) return;
@@ -311,7 +314,11 @@ __device__ __forceinline__ uint32_t band_block(const CollideArgs& a, uint32_t s)
   return z * a.plane_w + band * a.band_w + w;
 }
 
-template <typename real, int NC, bool SOLIDS>
+// COUNT: the variant that also counts every population store in a.counts
+// (one writer per slot of the output: the uniqueness of the reflected slots
+// and the completeness of the solid nodes' zeros); selected at run time by
+// lb_debug_count_writes, never by a step that does not ask for it.
+template <typename real, int NC, bool SOLIDS, bool COUNT = false>
 __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
   const uint32_t b = band_block(a, (blockIdx.x % 8u) * a.blocks_per_xcd + blockIdx.x / 8u);
   const uint32_t n0 = b * BLOCK + threadIdx.x;
@@ -494,6 +501,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
                   ((smask >> i) & 1u) ? n * uint32_t(sizeof(real)) : kOffNone, v);
       else if (smask & (1u << i))
         st32(fk + size_t(i) * N, n, v);
+      if (COUNT && ((smask >> i) & 1u)) atomicAdd(a.counts + (size_t(k) * Q + i) * N + n, 1u);
       // the link's post-collision value, for the lane that will take the link
       if (kDenseLinks<real>) {
         if (SOLIDS) lq.fs[k][i * 64 + lane] = v;
@@ -553,7 +561,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
       rk[k] = q.rho[k][src];
     }
     const real us[3] = {q.u[0][src], q.u[1][src], q.u[2][src]};
-    link_one<real, NC>(a, i, o, q.x[src], q.y[src], q.z[src], fs, rk, us, pid, lv);
+    link_one<real, NC, COUNT>(a, i, o, q.x[src], q.y[src], q.z[src], fs, rk, us, pid, lv);
   }
   if (!queued) {
     // past the wave's capacity: this lane walks its own links, reading back
@@ -567,7 +575,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
       const uint32_t sn = nbr_dyn(x, y, z, dir_c(PCX, i), dir_c(PCY, i), dir_c(PCZ, i), a.nx,
                                   a.ny, a.nz);
       const real un[3] = {ux, uy, uz};
-      link_one<real, NC>(a, i, ld32(a.owner, sn), x, y, z, fs, rho, un, pid, lv);
+      link_one<real, NC, COUNT>(a, i, ld32(a.owner, sn), x, y, z, fs, rho, un, pid, lv);
     }
   }
   if (a.acc) flush_runs<7>(a.acc, AC_FLIQ, pid, lv);
@@ -859,7 +867,9 @@ hipError_t launch_density(lb_ctx* c, const void* f) {
 template <typename real, int NC>
 static void collide_t(lb_ctx* c, const CollideArgs& a) {
   dim3 grid(8u * a.blocks_per_xcd);
-  if (c->has_solids)
+  if (c->has_solids && a.counts)
+    hipLaunchKernelGGL((k_collide<real, NC, true, true>), grid, dim3(BLOCK), 0, c->stream, a);
+  else if (c->has_solids)
     hipLaunchKernelGGL((k_collide<real, NC, true>), grid, dim3(BLOCK), 0, c->stream, a);
   else
     hipLaunchKernelGGL((k_collide<real, NC, false>), grid, dim3(BLOCK), 0, c->stream, a);
@@ -891,6 +901,7 @@ hipError_t launch_collide(lb_ctx* c, const void* fin, void* fout, const uint16_t
     for (int k = 0; k < 2; ++k) a.wall_rho[f][k] = P.wall_rho[f][k];
   }
   a.ubnd = reinterpret_cast<const double*>(wptr(c, c->wl.ubnd));
+  a.counts = forces ? c->write_counts : nullptr;  // not during the adjoint's recomputation
   a.L[0] = g.nx;
   a.L[1] = g.ny;
   a.L[2] = g.nz;

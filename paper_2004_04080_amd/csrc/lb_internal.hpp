@@ -93,6 +93,8 @@ struct lb_ctx {
   std::string err;
   // static scratch of lb_observables_noalloc on the context's device
   void* noalloc_scratch = nullptr;
+  // caller's [ncomp][19][N] counters of lb_debug_count_writes (null: off)
+  uint32_t* write_counts = nullptr;
 };
 
 namespace lbh {
