@@ -301,24 +301,24 @@ def coarsening(name: str, steps: int, every: int, precision: str = "fp32",
 
 
 def copy_probe(gib: float, reps: int = 5) -> dict:
-    """A plain device-to-device copy of known size: the measured copy bandwidth,
-    and the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    """The library's hand-written copy kernel (lb_probe_stream, 16-byte chunks)
+    over a buffer of known size: the measured copy bandwidth, and the
+    reference for scaling the FETCH_SIZE / WRITE_SIZE counters (each launch
+    reads and writes `gib` GiB exactly once)."""
+    import ctypes as C
     import torch
-    n = int(gib * (1 << 30))
-    a = torch.ones(n, dtype=torch.uint8, device="cuda:0")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return {"copy_bytes_read": n, "copy_bytes_written": n, "ms": round(ms, 4),
-            "GBps_read_plus_write": round(2 * n / (ms * 1e-3) / 1e9, 1)}
+    from paper_2004_04080_amd import binding as B
+    n = int(gib * (1 << 30)) // 16 * 16
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros_like(a)
+    ms = C.c_double()
+    B.check(B.lib().lb_probe_stream(2, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), n,
+                                    0, 0, 0, reps,
+                                    C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                    C.byref(ms)), "lb_probe_stream")
+    return {"copy_bytes_read": n, "copy_bytes_written": n, "launches": reps + 1,
+            "ms": round(ms.value, 4),
+            "GBps_read_plus_write": round(2 * n / (ms.value * 1e-3) / 1e9, 1)}
 
 
 def stream_probes(gib: float = 8.0, box=(512, 512, 512), reps: int = 10) -> dict:
@@ -392,7 +392,7 @@ def main():
                     help="comma-separated further boxes (C2,C3,C4,MT0) timed after the main "
                          "one and reported under other_workloads (same step counts)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
-                    help="only run a plain device copy of this many GiB and report it")
+                    help="only run the library's copy kernel over this many GiB and report it")
     ap.add_argument("--coarsening", type=int, default=0,
                     help="only run this many steps of --workload (FP32) and report the "
                          "average domain size every --every steps")
