@@ -168,6 +168,40 @@ def measured_traffic(workload: str, precision: str):
         return None
 
 
+STEP_COUNTERS = os.path.join(ROOT, "profiles", "step_T512_fp32_hbm_traffic.md")
+CSRC = os.path.join(ROOT, "paper_2004_04080_amd", "csrc")
+
+
+def step_traffic(w, precision: str, ms_per_step: float):
+    """Whole-step HBM traffic (rocprofv3 FETCH_SIZE + WRITE_SIZE over every
+    kernel of a step, copy-calibrated, from the committed summary) over the
+    step time just measured; None unless the summary's workload and
+    precision match and the library's sources are those it was taken on."""
+    if w.name != "T" or precision != "fp32":
+        return None
+    try:
+        text = open(STEP_COUNTERS).read()
+        block = text.split("```counters", 1)[1].split("```", 1)[0]
+        kv = dict(line.split(": ", 1) for line in block.strip().splitlines())
+        h = hashlib.sha256()
+        for f in sorted(os.listdir(CSRC)):
+            if f.endswith((".hip", ".hpp")) and not f.startswith("_"):
+                with open(os.path.join(CSRC, f), "rb") as fh:
+                    h.update(fh.read())
+        if h.hexdigest() != kv["source_sha256"]:
+            return None
+        b = float(kv["traffic_bytes_per_step"])
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+    gbps = b / (ms_per_step * 1e-3) / 1e9
+    return {"bytes_per_step": int(b), "bytes_per_node": round(b / w.N, 1),
+            "achieved_GBps": round(gbps, 1), "frac_of_peak": round(gbps / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_node": 322,
+            "algorithmic_GBps": round(322 * w.N / (ms_per_step * 1e-3) / 1e9, 1),
+            "algorithmic_frac": round(322 * w.N / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "source": "profiles/step_T512_fp32_hbm_traffic.md"}
+
+
 def roofline(w, res, es, precision):
     """Algorithmic bytes of one collide launch over its average duration."""
     K = w.ncomp
@@ -470,6 +504,7 @@ def main():
                    "nodes": w.N, "spheres": w.nparticles,
                    "fluid_nodes": res["fluid_nodes"], "links": res["links"]},
         "roofline": rl,
+        "step_traffic": step_traffic(w, args.precision, res["ms_per_step"]),
         "cpu_baseline": cpu,
         "fp64": fp64,
         "accuracy": acc,
