@@ -179,17 +179,26 @@ enum {
   LB_P_HAVEPREV = 49 /* 1 when FPREV/TPREV hold a previous half-step value     */
 };
 
+/* Infrastructure (no passage of the paper defines these): library version
+ * string; a static description of a status code; the last error message of
+ * a context (or of the last failed lb_init when ctx is NULL), owned by the
+ * library and valid until the next call on that context. */
 const char* lb_version(void);
 const char* lb_strerror(int status);
-/* Last error message of a context (or of the last failed lb_init when ctx is NULL). */
 const char* lb_last_error(const struct lb_ctx* ctx);
 
 /* D3Q19 velocities c [19][3] and weights w [19] in the library's order
  * (Sec. 2.1). Host only. */
 int lb_lattice(int32_t* c, double* w);
 
-/* Device buffer sizes for params. Host only; validates params.
- * Errors: LB_E_ARG (null or invalid parameters), LB_E_SHAPE (box too large). */
+/* Device buffer sizes for params: the two population buffers of the
+ * collide-stream sequence (Sec. 3.1; the pull form of Eq. bgk2, 2 x ncomp x
+ * 19 values per node), the pseudo-potential field (Eq. shanchen), the two
+ * owner maps of the moving-boundary scheme (Sec. 2.3), the sphere records
+ * and accumulators, the work buffer (lists, reductions, staging) and, with
+ * checkpoint_every > 0, the adjoint's checkpoints. Host only; validates
+ * params. Errors: LB_E_ARG (null or invalid parameters), LB_E_SHAPE (box too
+ * large: a population plane must stay below 4 GiB). */
 int lb_required_sizes(const lb_params* params, lb_sizes* out);
 
 /* Create a context on the caller's buffers and stream (hipStream_t, NULL =
@@ -355,11 +364,15 @@ int lb_probe_stream(int32_t kind, const void* src, void* dst, size_t bytes, int3
  * Walls or spheres required (LB_E_STATE). Slower; for tests only. */
 int lb_debug_count_writes(struct lb_ctx* ctx, void* counts);
 
-/* Wait for all work queued by the context. */
+/* Wait for all work queued by the context (infrastructure: synchronises the
+ * context's stream; the side stream of the map update joins that stream
+ * within every step). Errors: LB_E_ARG, LB_E_HIP. */
 int lb_sync(struct lb_ctx* ctx);
 
 /* Per-phase GPU timing with HIP events recorded on the context's stream around
- * the kernels of each phase of lb_step. lb_timing(ctx, 1) clears the totals
+ * the kernels of each phase of lb_step, the phases of the paper's step
+ * sequence (Sec. 3.1) whose throughput the paper reports per lattice update
+ * (Eq. glups). lb_timing(ctx, 1) clears the totals
  * and starts recording, lb_timing(ctx, 0) stops. lb_timing_read synchronises
  * and returns the summed milliseconds and launch counts per phase:
  * 0 moments (density), 1 sphere map/events/pairs, 2 virtual-density fills,
@@ -369,7 +382,9 @@ int lb_sync(struct lb_ctx* ctx);
 int lb_timing(struct lb_ctx* ctx, int enable);
 int lb_timing_read(struct lb_ctx* ctx, double ms[LB_NPHASE], int64_t count[LB_NPHASE]);
 
-/* Destroy a context (does not free the caller's buffers). NULL is ignored. */
+/* Destroy a context (infrastructure): releases the library's own objects
+ * (streams, events, the FFT plan) but not the caller's buffers. NULL is
+ * ignored. */
 void lb_free(struct lb_ctx* ctx);
 
 #ifdef __cplusplus
