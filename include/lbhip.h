@@ -341,8 +341,9 @@ int lb_domain_size(struct lb_ctx* ctx, void* work, size_t work_bytes, double* L,
 
 /* Streaming probes (measurement only, not part of the step): the time of a
  * plain bandwidth-bound kernel on this device, the ceiling against which the
- * step's kernels are read. kind 0 reads `bytes` of src (16-byte chunks; dst,
- * at least 1 KB, is only a sink that finite inputs never reach); kind 1
+ * step's kernels are read. kind 0 reads `bytes` of src (16-byte chunks; the
+ * first 16 bytes of dst are only a sink that finite inputs of order one never
+ * reach); kind 1
  * writes `bytes` of dst; kind 2 copies `bytes` from src to dst; kind 3 moves
  * two components of 19 FP32 planes of N = nx ny nz nodes in the pattern of
  * the fused step: plane i of node n is gathered from node n - c_i (D3Q19,

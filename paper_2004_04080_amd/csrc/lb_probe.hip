@@ -3,8 +3,9 @@
 // kernels, not part of the step.
 //
 //   kind 0  read:    every 16-byte chunk of src read once (a sum per lane is
-//                    stored into dst only when it equals -1.2345e30, which
-//                    finite inputs of order one never give)
+//                    stored into the first 16 bytes of dst only when it
+//                    equals -1.2345e30, which finite inputs of order one
+//                    never give)
 //   kind 1  write:   every 16-byte chunk of dst written once
 //   kind 2  copy:    src -> dst in 16-byte chunks (one read and one write)
 //   kind 3  collide: two components of 19 planes of N = nx ny nz floats; node
@@ -33,7 +34,7 @@ k_probe_read(const float4* __restrict__ src, size_t n16, uint32_t per_xcd, float
   if (t >= n16) return;
   const float4 v = src[t];
   const float s = v.x + v.y + v.z + v.w;
-  if (s == -1.2345e30f) sink[threadIdx.x] = s;
+  if (s == -1.2345e30f) sink[threadIdx.x & 3u] = s;  // within the first chunk of dst
 }
 
 __global__ void __launch_bounds__(PRB)
@@ -94,7 +95,7 @@ extern "C" int lb_probe_stream(int32_t kind, const void* src, void* dst, size_t 
   const uint64_t blocks = (items + PRB - 1) / PRB;
   const uint32_t per_xcd = uint32_t((blocks + 7) / 8);
   const dim3 grid(8u * per_xcd), blk(PRB);
-  float* sink = static_cast<float*>(dst);  // the read probe's sink (first PRB floats)
+  float* sink = static_cast<float*>(dst);  // the read probe's sink (first 4 floats)
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LB_E_HIP;
   auto launch = [&]() {
