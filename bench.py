@@ -170,6 +170,19 @@ def measured_traffic(workload: str, precision: str):
 
 STEP_COUNTERS = os.path.join(ROOT, "profiles", "step_T512_fp32_hbm_traffic.md")
 CSRC = os.path.join(ROOT, "paper_2004_04080_amd", "csrc")
+# the sources the kernels of lb_step are built from (the adjoint, domain-size,
+# allocation-free and probe sources do not run in a step)
+STEP_SOURCES = ("lb_api.hip", "lb_device.hpp", "lb_fluid.hip", "lb_internal.hpp",
+                "lb_particles.hip")
+
+
+def step_sources_sha256() -> str:
+    """sha256 over the step's sources, in the order of STEP_SOURCES."""
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def step_traffic(w, precision: str, ms_per_step: float):
@@ -183,12 +196,7 @@ def step_traffic(w, precision: str, ms_per_step: float):
         text = open(STEP_COUNTERS).read()
         block = text.split("```counters", 1)[1].split("```", 1)[0]
         kv = dict(line.split(": ", 1) for line in block.strip().splitlines())
-        h = hashlib.sha256()
-        for f in sorted(os.listdir(CSRC)):
-            if f.endswith((".hip", ".hpp")) and not f.startswith("_"):
-                with open(os.path.join(CSRC, f), "rb") as fh:
-                    h.update(fh.read())
-        if h.hexdigest() != kv["source_sha256"]:
+        if step_sources_sha256() != kv["source_sha256"]:
             return None
         b = float(kv["traffic_bytes_per_step"])
     except (OSError, IndexError, KeyError, ValueError):

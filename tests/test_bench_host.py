@@ -81,10 +81,10 @@ def test_counter_summary_applies_only_to_its_sources(tmp_path, monkeypatch):
 def test_step_traffic_applies_only_to_its_sources(tmp_path, monkeypatch):
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(bench.CSRC)):
-        if f.endswith((".hip", ".hpp")) and not f.startswith("_"):
-            with open(os.path.join(bench.CSRC, f), "rb") as fh:
-                h.update(fh.read())
+    for f in bench.STEP_SOURCES:
+        with open(os.path.join(bench.CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    assert h.hexdigest() == bench.step_sources_sha256()
     p = tmp_path / "s.md"
     monkeypatch.setattr(bench, "STEP_COUNTERS", str(p))
     w = types.SimpleNamespace(name="T", N=512 ** 3)
