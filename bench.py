@@ -439,6 +439,8 @@ def main():
                     help="only run this many steps of --workload (FP32) and report the "
                          "average domain size every --every steps")
     ap.add_argument("--every", type=int, default=1000)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the reverse-sweep leg (differentiation box) and print it")
     ap.add_argument("--janus", action="store_true",
                     help="coarsening with the benchmark's Janus wetting and lubrication")
     args = ap.parse_args()
@@ -448,6 +450,9 @@ def main():
         return
     if args.copy_probe > 0:
         print(json.dumps(copy_probe(args.copy_probe)), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps(adjoint_leg()), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
