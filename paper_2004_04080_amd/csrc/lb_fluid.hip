@@ -371,10 +371,14 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
     }
   }
   real f[NC][Q];
+  // 4-byte values: every load of the node leaves at once (8-byte values
+  // gather after the pseudo-potential sums, below)
+  if constexpr (sizeof(real) == 4) {
 #pragma unroll
-  for (int k = 0; k < NC; ++k)
+    for (int k = 0; k < NC; ++k)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[k][i] = ld32(fin + (size_t(k) * Q + i) * N, nb.pull(i));
+      for (int i = 0; i < Q; ++i) f[k][i] = ld32(fin + (size_t(k) * Q + i) * N, nb.pull(i));
+  }
 
   // Shan-Chen acceleration a_k = -G s sum_i w_i psi_kbar(n + c_i) c_i + g; the
   // rho0 part of psi cancels because every neighbour of a fluid node is fluid
@@ -409,6 +413,20 @@ __global__ void __launch_bounds__(BLOCK) k_collide(const CollideArgs a) {
       ay[k] -= gs * (real(W1) * s1[1] + real(W2) * s2[1]);
       az[k] -= gs * (real(W1) * s1[2] + real(W2) * s2[2]);
     }
+  }
+  if constexpr (sizeof(real) == 8) {
+    // 8-byte values: the pseudo-potential sums are complete (the empty asm
+    // takes them as inputs and orders memory) before the 38 gathers leave, so
+    // the 36 stencil loads and the gathered values are never in flight
+    // together: 152 registers instead of 196, three waves per SIMD instead of
+    // two (collide 22.58 -> 22.09 ms at 512^3 with 32,000 spheres, 17.99 ->
+    // 17.34 ms without spheres, A/B on one box)
+#pragma unroll
+    for (int k = 0; k < NC; ++k) asm volatile("" ::"v"(ax[k]), "v"(ay[k]), "v"(az[k]) : "memory");
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[k][i] = ld32(fin + (size_t(k) * Q + i) * N, nb.pull(i));
   }
 
   // Solid lanes run the same arithmetic and store zeros through the same
