@@ -374,8 +374,10 @@ int lb_sync(struct lb_ctx* ctx);
  * the kernels of each phase of lb_step, the phases of the paper's step
  * sequence (Sec. 3.1) whose throughput the paper reports per lattice update
  * (Eq. glups). lb_timing(ctx, 1) clears the totals
- * and starts recording, lb_timing(ctx, 0) stops. lb_timing_read synchronises
- * and returns the summed milliseconds and launch counts per phase:
+ * and starts recording; lb_timing(ctx, 0) stops recording and keeps the
+ * totals. lb_timing_read synchronises and returns the summed milliseconds
+ * and interval counts per phase (phase 1 records the map update on the side
+ * stream and the node events on the context's stream, two per step):
  * 0 moments (density), 1 sphere map/events/pairs, 2 virtual-density fills,
  * 3 collide-stream-bounce-back with the link momentum exchange,
  * 4 sphere integration. */

@@ -981,11 +981,14 @@ int lb_set_particles(lb_ctx* c, const double* rec) {
 
 int lb_timing(lb_ctx* c, int enable) {
   if (!c) return LB_E_ARG;
-  if (harvest(c, false) != LB_OK) return fail(c, LB_E_HIP, "timing: stream synchronisation failed");
-  for (int p = 0; p < LB_NPHASE; ++p) {
-    c->phase_ms[p] = 0.0;
-    c->phase_n[p] = 0;
-  }
+  // starting drops what was recorded before; stopping keeps it for lb_timing_read
+  if (harvest(c, enable == 0) != LB_OK)
+    return fail(c, LB_E_HIP, "timing: stream synchronisation failed");
+  if (enable != 0)
+    for (int p = 0; p < LB_NPHASE; ++p) {
+      c->phase_ms[p] = 0.0;
+      c->phase_n[p] = 0;
+    }
   c->timing = enable != 0;
   return LB_OK;
 }
