@@ -67,3 +67,38 @@ def test_reference_densities_and_normalisation_fp32_step():
     for k in ("Fliq", "Tliq", "FSC", "TSC"):
         assert ep[k] < 1e-5, k
     lat.close()
+
+
+def test_unequal_tau_spheres_without_rotation_fp64():
+    """Unequal relaxation times (the mixture relaxation rate of Eq. viscosity)
+    with moving spheres between moving walls, the orientation update switched
+    off (rotate = False), and a pair in Hertz contact with non-default
+    constants (K = 5, onset 7.5, cap 6.2): FP64 within 1e-12 after 1 and 10
+    steps."""
+    w = synth.Workload("tau", *SHAPE, seed=synth.BASE_SEED + 92)
+    x = np.array([[8.0, 10.0, 9.0], [14.6, 10.3, 9.2], [19.5, 4.2, 12.5], [4.8, 15.6, 6.1]])
+    rng = np.random.default_rng(92)
+    v = 0.03 * (2 * rng.random((4, 3)) - 1)
+    om = 0.02 * (2 * rng.random((4, 3)) - 1)
+    kw = dict(ncomp=2, tau=(0.7, 1.2), G=0.6, g=(0.0, 1e-5, 0.0), walls=True,
+              wall_u_lo=(0.0, -0.01, 0.0), wall_u_hi=(0.01, 0.0, 0.0), radius=3.0,
+              particle_density=1.2, hertz_K=5.0, hertz_d0=7.5, hertz_rcap=6.2, rotate=False)
+    o, lat = make_pair(SHAPE, w.densities(), x=x, v=v, w=om, precision="fp64", **kw)
+    done = 0
+    for h in (1, 10):
+        o.step(h - done)
+        lat.step(h - done)
+        done = h
+        e = compare(o, lat)
+        ep = compare_particles(o, lat)
+        print(f"[reference] unequal tau t={h}",
+              {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in {**e, **ep}.items()},
+              flush=True)
+        assert e.pop("owner_equal")
+        for k, v in {**e, **ep}.items():
+            assert v <= 1e-12, (h, k, v)
+    # the orientation stays as it started, the spin as given
+    rec = lat.particles()
+    from oracle import REC
+    assert np.all(rec[:, REC["q"]] == 1.0) and np.all(rec[:, REC["q"] + 1:REC["q"] + 4] == 0.0)
+    lat.close()
