@@ -315,8 +315,14 @@ constexpr uint32_t kNeg2[3] = {dir_set(0, -1, 2), dir_set(1, -1, 2), dir_set(2, 
 // The map holds sphere p around the centre at offset `which` of its record.
 // Entries of one sphere sit together in each list. Along an axis shorter than
 // the box, one period of the box is walked, so that no node is listed twice.
-__global__ void __launch_bounds__(PBLOCK) k_sphere_lists(PArgs a, NodeList fl, NodeList ev,
-                                                         int which) {
+// CAP64: at most 64 registers (eight waves per SIMD). In FP64 the kernel
+// runs beside a moments pass whose waves hold 64 registers each, and a wave
+// of its own must fit in what one of them frees (side stream 9.2 -> 6.5 ms
+// at 512^3 with 32,000 spheres); beside the FP32 pass it runs faster with
+// the compiler's own register count (3.8 against 5.2 ms capped).
+template <bool CAP64>
+__global__ void __launch_bounds__(PBLOCK, CAP64 ? 8 : 1) k_sphere_lists(PArgs a, NodeList fl,
+                                                                       NodeList ev, int which) {
   __shared__ Stage<1024> sf;
   __shared__ Stage<512> se;
   const bool events = ev.list != nullptr;
@@ -339,6 +345,35 @@ __global__ void __launch_bounds__(PBLOCK) k_sphere_lists(PArgs a, NodeList fl, N
   const uint16_t me = uint16_t(p + 1);
   const int tx = int(threadIdx.x & 15u), ty = int(threadIdx.x >> 4);
   const double deep2 = a.R > 1.5 ? (a.R - 1.5) * (a.R - 1.5) : -1.0;
+  // Which map reads can decide anything: the sphere owns a node of a map
+  // only inside its ball there (the raster's test, |d|^2 < R^2 off the wall
+  // layers), so outside it the new map cannot hold this sphere; a destroyed
+  // node is the sphere's now and was fluid, so it is not surely inside the
+  // old ball; a created node is fluid now and was the sphere's, so it is
+  // inside the old ball and not surely inside the new one. "Maybe" and
+  // "surely" inside are FP32 tests of |d|^2 against R^2 +- eps2, where eps2
+  // bounds the FP32 error of |d|^2 for a node within R + 1 of the centre:
+  // coordinates and centre rounded to FP32 (each within L 2^-24), the
+  // subtraction, the choice of periodic image next to L/2, the squares and
+  // the sum (with a factor 2 to spare). The lists are those of reading every
+  // node; only the reads that cannot change them are skipped.
+  const double Lmax = fmax(a.L[0], fmax(a.L[1], a.L[2]));
+  const double eps2 = 8.0 * (a.R + 1.0) * (Lmax + a.R + 1.0) * 0x1p-23;
+  const float R2lo = float(a.R * a.R - eps2), R2hi = float(a.R * a.R + eps2);
+  const float cnf[3] = {float(c[0]), float(c[1]), float(c[2])};
+  const float cof[3] = {float(P[PS_XRA]), float(P[PS_XRA + 1]), float(P[PS_XRA + 2])};
+  const float Lf[3] = {float(a.L[0]), float(a.L[1]), float(a.L[2])};
+  auto dist2f = [&](uint32_t wx, uint32_t wy, uint32_t wz, const float* ctr) {
+    float s2 = 0.0f;
+    const uint32_t wc[3] = {wx, wy, wz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      float v = float(wc[d]) - ctr[d];
+      v = fabsf(v + v) < Lf[d] ? v : v - Lf[d] * rintf(v / Lf[d]);
+      s2 += v * v;
+    }
+    return s2;
+  };
   if (threadIdx.x == 0) sf.staged = se.staged = 0;
   // trip counts are uniform over the workgroup: every thread reaches the barriers
   for (int k = 0; k < nb2; ++k)
@@ -351,7 +386,17 @@ __global__ void __launch_bounds__(PBLOCK) k_sphere_lists(PArgs a, NodeList fl, N
           const uint32_t wy = uint32_t(wrap_box(b.lo[1] + j, a.ny));
           const uint32_t wz = uint32_t(wrap_box(b.lo[2] + k, a.nz));
           n = wx + uint32_t(a.nx) * (wy + uint32_t(a.ny) * wz);
-          const uint16_t w = a.own_new[n];
+          const bool wall = a.walls && (wz == 0 || wz == uint32_t(a.nz) - 1);
+          const float n2 = dist2f(wx, wy, wz, cnf);
+          const bool maybe_new = !wall && n2 < R2hi, sure_new = !wall && n2 < R2lo;
+          bool maybe_old = false, sure_old = false;
+          if (events) {
+            const float o2 = dist2f(wx, wy, wz, cof);
+            maybe_old = !wall && o2 < R2hi;
+            sure_old = !wall && o2 < R2lo;
+          }
+          const bool moved = events && ((maybe_new && !sure_old) || (maybe_old && !sure_new));
+          const uint16_t w = (maybe_new || moved) ? a.own_new[n] : uint16_t(0);
           // a node closer than R - 3/2 to the centre has every neighbour (at
           // most sqrt 2 away) inside the ball: none of them is fluid
           const double dx = min_image(double(wx) - c[0], a.L[0]);
@@ -363,7 +408,7 @@ __global__ void __launch_bounds__(PBLOCK) k_sphere_lists(PArgs a, NodeList fl, N
             for (int d = 1; d < Q; ++d)
               if (a.own_new[nbr.push(d)] == 0) mask |= 1u << d;
           }
-          if (events) {
+          if (moved) {
             const uint16_t o = a.own_old[n];
             if (o == 0 && w == me) evc = 0x80000000u | me;   // destroyed
             else if (w == 0 && o == me) evc = me;           // created
@@ -929,10 +974,15 @@ hipError_t launch_sphere_lists(lb_ctx* c, const uint16_t* owner, const uint16_t*
   if (e == hipSuccess && owner_old) e = launch_zero(ev.count, sizeof(int32_t), s);
   if (e != hipSuccess) return e;
   if (!owner_old) ev.list = nullptr;
-  if (c->nparticles > 0)
-    hipLaunchKernelGGL(k_sphere_lists, dim3(c->nparticles), dim3(PBLOCK), 0, s,
-                       pargs(c, const_cast<uint16_t*>(owner), owner_old ? owner_old : owner), fl,
-                       ev, which);
+  if (c->nparticles > 0) {
+    const PArgs a = pargs(c, const_cast<uint16_t*>(owner), owner_old ? owner_old : owner);
+    if (c->geo.prec == LB_FP64)
+      hipLaunchKernelGGL(k_sphere_lists<true>, dim3(c->nparticles), dim3(PBLOCK), 0, s, a, fl,
+                         ev, which);
+    else
+      hipLaunchKernelGGL(k_sphere_lists<false>, dim3(c->nparticles), dim3(PBLOCK), 0, s, a, fl,
+                         ev, which);
+  }
   return hipGetLastError();
 }
 
