@@ -143,7 +143,9 @@ def run_gpu(w, rho, x, precision, steps, warmup, want_roofline, want_fields=Fals
     return out
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_collide_T512_fp32_hbm_counters.md")
+# committed rocprofv3 counter summaries of the 512^3 bench box, per precision
+COUNTERS = {pr: os.path.join(ROOT, "profiles", f"k_collide_T512_{pr}_hbm_counters.md")
+            for pr in ("fp32", "fp64")}
 COLLIDE_SOURCES = ("paper_2004_04080_amd/csrc/lb_fluid.hip", "paper_2004_04080_amd/csrc/lb_device.hpp")
 
 
@@ -151,10 +153,10 @@ def measured_traffic(workload: str, precision: str):
     """HBM bytes per collide launch from the committed rocprofv3 FETCH_SIZE and
     WRITE_SIZE counters (scaled by the copy calibration), or None when they were
     taken on another workload or the collide sources changed since."""
-    if workload != "T" or precision != "fp32":
+    if workload != "T" or precision not in COUNTERS:
         return None
     try:
-        text = open(COUNTERS).read()
+        text = open(COUNTERS[precision]).read()
         block = text.split("```counters", 1)[1].split("```", 1)[0]
         kv = dict(line.split(": ", 1) for line in block.strip().splitlines())
         h = hashlib.sha256()
@@ -168,7 +170,11 @@ def measured_traffic(workload: str, precision: str):
         return None
 
 
-STEP_COUNTERS = os.path.join(ROOT, "profiles", "step_T512_fp32_hbm_traffic.md")
+STEP_COUNTERS = {pr: os.path.join(ROOT, "profiles", f"step_T512_{pr}_hbm_traffic.md")
+                 for pr in ("fp32", "fp64")}
+# the method's minimum HBM bytes per node and step: populations read and
+# written once, the pseudo-potential written and read once, the owner map read
+MIN_BYTES_PER_NODE = {"fp32": 322, "fp64": 642}
 CSRC = os.path.join(ROOT, "paper_2004_04080_amd", "csrc")
 # the sources the kernels of lb_step are built from (the adjoint, domain-size,
 # allocation-free and probe sources do not run in a step)
@@ -190,10 +196,10 @@ def step_traffic(w, precision: str, ms_per_step: float):
     kernel of a step, copy-calibrated, from the committed summary) over the
     step time just measured; None unless the summary's workload and
     precision match and the library's sources are those it was taken on."""
-    if w.name != "T" or precision != "fp32":
+    if w.name != "T" or precision not in STEP_COUNTERS:
         return None
     try:
-        text = open(STEP_COUNTERS).read()
+        text = open(STEP_COUNTERS[precision]).read()
         block = text.split("```counters", 1)[1].split("```", 1)[0]
         kv = dict(line.split(": ", 1) for line in block.strip().splitlines())
         if step_sources_sha256() != kv["source_sha256"]:
@@ -202,12 +208,14 @@ def step_traffic(w, precision: str, ms_per_step: float):
     except (OSError, IndexError, KeyError, ValueError):
         return None
     gbps = b / (ms_per_step * 1e-3) / 1e9
+    m = MIN_BYTES_PER_NODE[precision]
+    alg = m * w.N / (ms_per_step * 1e-3) / 1e9
     return {"bytes_per_step": int(b), "bytes_per_node": round(b / w.N, 1),
             "achieved_GBps": round(gbps, 1), "frac_of_peak": round(gbps / HBM_PEAK_GBS, 4),
-            "algorithmic_bytes_per_node": 322,
-            "algorithmic_GBps": round(322 * w.N / (ms_per_step * 1e-3) / 1e9, 1),
-            "algorithmic_frac": round(322 * w.N / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "source": "profiles/step_T512_fp32_hbm_traffic.md"}
+            "algorithmic_bytes_per_node": m,
+            "algorithmic_GBps": round(alg, 1),
+            "algorithmic_frac": round(alg / HBM_PEAK_GBS, 4),
+            "source": os.path.relpath(STEP_COUNTERS[precision], ROOT)}
 
 
 def roofline(w, res, es, precision):
@@ -479,6 +487,7 @@ def main():
         fp64 = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "steps": fsteps,
                 "ms_per_step": round(r64["ms_per_step"], 3),
                 "roofline": roofline(w, r64, 8, "fp64"),
+                "step_traffic": step_traffic(w, "fp64", r64["ms_per_step"]),
                 "phases_ms_per_step": {k: round(v[0] / max(fsteps, 1), 4)
                                        for k, v in r64["phases"].items()}}
         acc = accuracy(res.pop("fields"), r64.pop("fields"), cmp_at)

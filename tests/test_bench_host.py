@@ -68,14 +68,18 @@ def test_counter_summary_applies_only_to_its_sources(tmp_path, monkeypatch):
     for f in bench.COLLIDE_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    p = tmp_path / "c.md"
-    monkeypatch.setattr(bench, "COUNTERS", str(p))
+    p, q = tmp_path / "c.md", tmp_path / "c64.md"
+    monkeypatch.setattr(bench, "COUNTERS", {"fp32": str(p), "fp64": str(q)})
     _counter_file(p, h.hexdigest(), 123456789)
     assert bench.measured_traffic("T", "fp32") == 123456789
-    assert bench.measured_traffic("T", "fp64") is None
+    assert bench.measured_traffic("T", "fp64") is None      # no summary taken in FP64
+    _counter_file(q, h.hexdigest(), 987654321)
+    assert bench.measured_traffic("T", "fp64") == 987654321
     assert bench.measured_traffic("C4", "fp32") is None
+    assert bench.measured_traffic("T", "fp16") is None
     _counter_file(p, "0" * 64, 123456789)
     assert bench.measured_traffic("T", "fp32") is None
+    assert bench.measured_traffic("T", "fp64") == 987654321
 
 
 def test_step_traffic_applies_only_to_its_sources(tmp_path, monkeypatch):
@@ -85,8 +89,8 @@ def test_step_traffic_applies_only_to_its_sources(tmp_path, monkeypatch):
         with open(os.path.join(bench.CSRC, f), "rb") as fh:
             h.update(fh.read())
     assert h.hexdigest() == bench.step_sources_sha256()
-    p = tmp_path / "s.md"
-    monkeypatch.setattr(bench, "STEP_COUNTERS", str(p))
+    p, q = tmp_path / "s.md", tmp_path / "s64.md"
+    monkeypatch.setattr(bench, "STEP_COUNTERS", {"fp32": str(p), "fp64": str(q)})
     w = types.SimpleNamespace(name="T", N=512 ** 3)
     p.write_text("```counters\nsource_sha256: %s\ntraffic_bytes_per_step: 75000000000\n```\n"
                  % h.hexdigest())
@@ -95,6 +99,12 @@ def test_step_traffic_applies_only_to_its_sources(tmp_path, monkeypatch):
     assert abs(st["achieved_GBps"] - 5000.0) < 0.1
     assert st["algorithmic_bytes_per_node"] == 322
     assert bench.step_traffic(w, "fp64", 15.0) is None
+    q.write_text("```counters\nsource_sha256: %s\ntraffic_bytes_per_step: 150000000000\n```\n"
+                 % h.hexdigest())
+    st = bench.step_traffic(w, "fp64", 30.0)
+    assert abs(st["achieved_GBps"] - 5000.0) < 0.1
+    assert st["algorithmic_bytes_per_node"] == 642
+    assert abs(st["algorithmic_GBps"] - 642 * 512 ** 3 / 30e-3 / 1e9) < 0.1
     p.write_text("```counters\nsource_sha256: %s\ntraffic_bytes_per_step: 1\n```\n" % ("f" * 64))
     assert bench.step_traffic(w, "fp32", 15.0) is None
 
