@@ -225,6 +225,15 @@ int lb_add_particles(struct lb_ctx* ctx, int32_t n, const double* x, const doubl
  * 1/2 node per step is flagged and reported by the next synchronising call.
  * With checkpoint_every > 0 the steps are recorded for lb_backward
  * (LB_E_CAPACITY beyond max_record_steps).
+ * Graph capture: a step issues only kernel launches and event records and
+ * waits (buffers are cleared by a kernel, not a memset), so a caller may
+ * capture lb_step on a non-default context stream into a HIP graph once the
+ * context has stepped eagerly at least once (the side stream and its events
+ * then exist). A graph of an even number of steps ends on the buffers it
+ * starts from and may be replayed any number of times; the context's step
+ * counter (lb_obs.step) advances when steps are captured, not when they are
+ * replayed. Not with checkpoint_every > 0 or with per-phase timing on, whose
+ * host-side records would not follow the replays.
  * Errors: LB_E_ARG, LB_E_HIP, LB_E_CAPACITY. */
 int lb_step(struct lb_ctx* ctx, int32_t nsteps);
 
