@@ -238,7 +238,7 @@ def roofline(w, res, es, precision):
 def cpu_baseline():
     """The serial FP64 oracle on a bounded sample of the workload: a 128^3 box
     with the same fluid parameters and sphere volume fraction (500 spheres of
-    radius 5.5), timed over 2 steps on one host thread."""
+    radius 5.5), timed over 8 steps (about 10 s) on one host thread."""
     import oracle as O
     import synth
     w = synth.workload("C3")
@@ -247,7 +247,7 @@ def cpu_baseline():
     o = O.Oracle(p, w.densities())
     o.add_particles(w.centres())
     t = time.time()
-    steps = 2
+    steps = 8
     o.step(steps)
     dt = time.time() - t
     return {"value": round(w.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,

@@ -680,6 +680,40 @@ __device__ __forceinline__ double hertz_mag(double r, double K, double d0, doubl
   return 2.5 * K * h * sqrt(h);
 }
 
+// The pair force on sphere p (record xp) from sphere q (record xq), added to
+// F: Hertz repulsion (Eq. hertzpot) and lubrication (Eq. libric) along the
+// line of centres of the nearest periodic images; `near` is set when the
+// centres are closer than 2R + 1/2 (the two may share nodes).
+__device__ __forceinline__ void pair_term(const CellArgs& a, const double* xp, const double* xq,
+                                          double F[3], bool& near) {
+  const double d[3] = {min_image(xq[0] - xp[0], a.L[0]), min_image(xq[1] - xp[1], a.L[1]),
+                       min_image(xq[2] - xp[2], a.L[2])};
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  near = near || !(r >= 2.0 * a.R + 0.5);
+  const double mag = hertz_mag(r, a.K, a.d0, a.rcap);
+  if (mag != 0.0)
+    for (int e = 0; e < 3; ++e) F[e] -= mag * d[e] / r;
+  const double h = r - 2.0 * a.R;
+  if (a.lub_mu > 0.0 && h < a.lub_hn) {
+    const double he = fmax(h, a.lub_hcap);
+    const double* vp = xp + PS_V;
+    const double* vq = xq + PS_V;
+    double vn = 0.0;
+    for (int e = 0; e < 3; ++e) vn += (vp[e] - vq[e]) * d[e] / r;
+    const double fl =
+        -6.0 * M_PI * a.lub_mu * 0.25 * a.R * a.R * (1.0 / he - 1.0 / a.lub_hn) * vn;
+    for (int e = 0; e < 3; ++e) F[e] += fl * d[e] / r;
+  }
+}
+
+// Mirror image of a sphere across each wall plane (the same Hertz law).
+__device__ __forceinline__ void wall_term(const CellArgs& a, const double* xp, double F[3]) {
+  if (!a.walls) return;
+  F[2] += hertz_mag(2.0 * (xp[2] - a.zlo), a.K, a.d0, a.rcap);
+  F[2] -= hertz_mag(2.0 * (a.zhi - xp[2]), a.K, a.d0, a.rcap);
+}
+
+// One thread per sphere over the 27 neighbouring cells of the cell list.
 __global__ void k_pairs(CellArgs a) {
   const int p = blockIdx.x * PBLOCK + threadIdx.x;
   if (p >= a.np) return;
@@ -687,7 +721,7 @@ __global__ void k_pairs(CellArgs a) {
   int ci[3];
   for (int d = 0; d < 3; ++d) ci[d] = cell_index(xp[d], a.cs[d], a.nc[d]);
   double F[3] = {0, 0, 0};
-  bool near = false;  // another centre closer than 2R + 1/2: the two may share nodes
+  bool near = false;
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
     // visit each neighbouring cell once, also when there are fewer than 3 cells
@@ -702,36 +736,49 @@ __global__ void k_pairs(CellArgs a) {
         const int c = cx + a.nc[0] * (cy + a.nc[1] * cz);
         for (int s = a.start[c]; s < a.start[c + 1]; ++s) {
           const int q = a.ids[s];
-          if (q == p) continue;
-          const double* xq = a.ps + size_t(q) * PSTRIDE;
-          const double d[3] = {min_image(xq[0] - xp[0], a.L[0]), min_image(xq[1] - xp[1], a.L[1]),
-                               min_image(xq[2] - xp[2], a.L[2])};
-          const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-          near = near || !(r >= 2.0 * a.R + 0.5);
-          const double mag = hertz_mag(r, a.K, a.d0, a.rcap);
-          if (mag != 0.0)
-            for (int e = 0; e < 3; ++e) F[e] -= mag * d[e] / r;
-          // lubrication (Eq. libric) along the line of centres
-          const double h = r - 2.0 * a.R;
-          if (a.lub_mu > 0.0 && h < a.lub_hn) {
-            const double he = fmax(h, a.lub_hcap);
-            const double* vp = xp + PS_V;
-            const double* vq = xq + PS_V;
-            double vn = 0.0;
-            for (int e = 0; e < 3; ++e) vn += (vp[e] - vq[e]) * d[e] / r;
-            const double fl = -6.0 * M_PI * a.lub_mu * 0.25 * a.R * a.R *
-                              (1.0 / he - 1.0 / a.lub_hn) * vn;
-            for (int e = 0; e < 3; ++e) F[e] += fl * d[e] / r;
-          }
+          if (q != p) pair_term(a, xp, a.ps + size_t(q) * PSTRIDE, F, near);
         }
       }
-  if (a.walls) {  // mirror image across each wall plane
-    F[2] += hertz_mag(2.0 * (xp[2] - a.zlo), a.K, a.d0, a.rcap);
-    F[2] -= hertz_mag(2.0 * (a.zhi - xp[2]), a.K, a.d0, a.rcap);
-  }
+  wall_term(a, xp, F);
   double* A = a.acc + size_t(p) * ASTRIDE;
   for (int e = 0; e < 3; ++e) A[AC_FH + e] = F[e];
   A[AC_NEAR] = near ? 1.0 : 0.0;
+}
+
+// Every pair at once, for a few spheres: one wave per sphere, its lanes over
+// the other spheres, then a butterfly sum (the same order on every run, and
+// every lane ends with the same bits). The cell list costs five dependent
+// kernels and a serial walk over 27 cells per thread, a chain of memory round
+// trips that sets the map update of a small box; here the sum takes a few
+// round trips. The wave writes the sphere's whole accumulator record (zeros,
+// the pair force and the near flag), which takes the place of the record
+// clear of the cell-list path. Far pairs add exactly zero, so the forces are
+// those of the cell list up to the order of the sums.
+constexpr int kAllPairsMax = 1024;
+static_assert(ASTRIDE <= 64, "one lane per accumulator entry");
+__global__ void __launch_bounds__(PBLOCK) k_pairs_all(CellArgs a) {
+  const int p = int(blockIdx.x) * (PBLOCK / 64) + int(threadIdx.x) / 64;
+  if (p >= a.np) return;  // whole waves
+  const int lane = __lane_id();
+  const double* xp = a.ps + size_t(p) * PSTRIDE;
+  double F[3] = {0, 0, 0};
+  bool near = false;
+  for (int q = lane; q < a.np; q += 64)
+    if (q != p) pair_term(a, xp, a.ps + size_t(q) * PSTRIDE, F, near);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) F[e] += __shfl_xor(F[e], off);
+  near = __ballot(near) != 0ull;
+  wall_term(a, xp, F);
+  if (lane < ASTRIDE) {
+    double v = 0.0;
+    if (lane == AC_FH) v = F[0];
+    if (lane == AC_FH + 1) v = F[1];
+    if (lane == AC_FH + 2) v = F[2];
+    if (lane == AC_NEAR) v = near ? 1.0 : 0.0;
+    a.acc[size_t(p) * ASTRIDE + lane] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -899,9 +946,8 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   const uint16_t* own_old = static_cast<const uint16_t*>(c->B.owner[c->own_old]);
   const PArgs a = pargs(c, own_new, own_old);
   const dim3 gp(c->nparticles), bp(PBLOCK);
-  hipError_t e0 = launch_zero(pacc(c), size_t(c->nparticles) * ASTRIDE * sizeof(double), s);
-  if (e0 != hipSuccess) return e0;
-  // Hertz pairs through the cell list
+  // Hertz and lubrication pairs: all at once for a few spheres, else through
+  // the cell list
   CellArgs ca;
   ca.ps = pstate(c);
   ca.acc = pacc(c);
@@ -926,14 +972,22 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   ca.lub_mu = c->P.lub_mu;
   ca.lub_hn = c->P.lub_hn;
   ca.lub_hcap = c->P.lub_hcap;
-  hipError_t e = launch_zero(ca.count, size_t(ncell) * sizeof(int32_t), s);
-  if (e != hipSuccess) return e;
-  const dim3 gt((c->nparticles + PBLOCK - 1) / PBLOCK);
-  hipLaunchKernelGGL(k_cell_count, gt, bp, 0, s, ca);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanThreads), 0, s, ca.count, ca.start, ncell);
-  hipLaunchKernelGGL(k_cell_fill, gt, bp, 0, s, ca);
-  hipLaunchKernelGGL(k_cell_sort, dim3((ncell + PBLOCK - 1) / PBLOCK), bp, 0, s, ca, ncell);
-  hipLaunchKernelGGL(k_pairs, gt, bp, 0, s, ca);
+  hipError_t e;
+  if (c->nparticles <= kAllPairsMax) {
+    const int per = PBLOCK / 64;
+    hipLaunchKernelGGL(k_pairs_all, dim3((c->nparticles + per - 1) / per), bp, 0, s, ca);
+  } else {
+    e = launch_zero(pacc(c), size_t(c->nparticles) * ASTRIDE * sizeof(double), s);
+    if (e != hipSuccess) return e;
+    e = launch_zero(ca.count, size_t(ncell) * sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    const dim3 gt((c->nparticles + PBLOCK - 1) / PBLOCK);
+    hipLaunchKernelGGL(k_cell_count, gt, bp, 0, s, ca);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanThreads), 0, s, ca.count, ca.start, ncell);
+    hipLaunchKernelGGL(k_cell_fill, gt, bp, 0, s, ca);
+    hipLaunchKernelGGL(k_cell_sort, dim3((ncell + PBLOCK - 1) / PBLOCK), bp, 0, s, ca, ncell);
+    hipLaunchKernelGGL(k_pairs, gt, bp, 0, s, ca);
+  }
   // the new map: cleared, walls, spheres at the current centres
   e = launch_zero(own_new, size_t(c->geo.N) * sizeof(uint16_t), s);
   if (e != hipSuccess) return e;
