@@ -680,12 +680,15 @@ __device__ __forceinline__ double hertz_mag(double r, double K, double d0, doubl
   return 2.5 * K * h * sqrt(h);
 }
 
-// The pair force on sphere p (record xp) from sphere q (record xq), added to
-// F: Hertz repulsion (Eq. hertzpot) and lubrication (Eq. libric) along the
-// line of centres of the nearest periodic images; `near` is set when the
-// centres are closer than 2R + 1/2 (the two may share nodes).
-__device__ __forceinline__ void pair_term(const CellArgs& a, const double* xp, const double* xq,
-                                          double F[3], bool& near) {
+// The pair force on sphere p (centre xp, state record rp) from sphere q
+// (centre xq, record rq), added to F: Hertz repulsion (Eq. hertzpot) and
+// lubrication (Eq. libric) along the line of centres of the nearest periodic
+// images; `near` is set when the centres are closer than 2R + 1/2 (the two
+// may share nodes). The velocities are read from the records only for a pair
+// within the lubrication range.
+__device__ __forceinline__ void pair_term(const CellArgs& a, const double xp[3], const double* rp,
+                                          const double xq[3], const double* rq, double F[3],
+                                          bool& near) {
   const double d[3] = {min_image(xq[0] - xp[0], a.L[0]), min_image(xq[1] - xp[1], a.L[1]),
                        min_image(xq[2] - xp[2], a.L[2])};
   const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -696,8 +699,8 @@ __device__ __forceinline__ void pair_term(const CellArgs& a, const double* xp, c
   const double h = r - 2.0 * a.R;
   if (a.lub_mu > 0.0 && h < a.lub_hn) {
     const double he = fmax(h, a.lub_hcap);
-    const double* vp = xp + PS_V;
-    const double* vq = xq + PS_V;
+    const double* vp = rp + PS_V;
+    const double* vq = rq + PS_V;
     double vn = 0.0;
     for (int e = 0; e < 3; ++e) vn += (vp[e] - vq[e]) * d[e] / r;
     const double fl =
@@ -707,7 +710,7 @@ __device__ __forceinline__ void pair_term(const CellArgs& a, const double* xp, c
 }
 
 // Mirror image of a sphere across each wall plane (the same Hertz law).
-__device__ __forceinline__ void wall_term(const CellArgs& a, const double* xp, double F[3]) {
+__device__ __forceinline__ void wall_term(const CellArgs& a, const double xp[3], double F[3]) {
   if (!a.walls) return;
   F[2] += hertz_mag(2.0 * (xp[2] - a.zlo), a.K, a.d0, a.rcap);
   F[2] -= hertz_mag(2.0 * (a.zhi - xp[2]), a.K, a.d0, a.rcap);
@@ -717,7 +720,8 @@ __device__ __forceinline__ void wall_term(const CellArgs& a, const double* xp, d
 __global__ void k_pairs(CellArgs a) {
   const int p = blockIdx.x * PBLOCK + threadIdx.x;
   if (p >= a.np) return;
-  const double* xp = a.ps + size_t(p) * PSTRIDE;
+  const double* rp = a.ps + size_t(p) * PSTRIDE;
+  const double xp[3] = {rp[0], rp[1], rp[2]};
   int ci[3];
   for (int d = 0; d < 3; ++d) ci[d] = cell_index(xp[d], a.cs[d], a.nc[d]);
   double F[3] = {0, 0, 0};
@@ -736,7 +740,10 @@ __global__ void k_pairs(CellArgs a) {
         const int c = cx + a.nc[0] * (cy + a.nc[1] * cz);
         for (int s = a.start[c]; s < a.start[c + 1]; ++s) {
           const int q = a.ids[s];
-          if (q != p) pair_term(a, xp, a.ps + size_t(q) * PSTRIDE, F, near);
+          if (q == p) continue;
+          const double* rq = a.ps + size_t(q) * PSTRIDE;
+          const double xq[3] = {rq[0], rq[1], rq[2]};
+          pair_term(a, xp, rp, xq, rq, F, near);
         }
       }
   wall_term(a, xp, F);
@@ -745,38 +752,68 @@ __global__ void k_pairs(CellArgs a) {
   A[AC_NEAR] = near ? 1.0 : 0.0;
 }
 
-// Every pair at once, for a few spheres: one wave per sphere, its lanes over
-// the other spheres, then a butterfly sum (the same order on every run, and
-// every lane ends with the same bits). The cell list costs five dependent
-// kernels and a serial walk over 27 cells per thread, a chain of memory round
-// trips that sets the map update of a small box; here the sum takes a few
-// round trips. The wave writes the sphere's whole accumulator record (zeros,
-// the pair force and the near flag), which takes the place of the record
-// clear of the cell-list path. Far pairs add exactly zero, so the forces are
-// those of the cell list up to the order of the sums.
+// Every pair at once, for a few spheres: one workgroup per sphere, each
+// thread over at most kPairsPer others, whose centres it loads together
+// before any arithmetic. The map update runs beside the density pass, whose
+// gathers keep the memory system full and every dependent round trip long;
+// the cell list costs five dependent kernels and a serial walk over 27 cells
+// per thread, and a loop with one round trip per other sphere costs as much,
+// while here the sum takes one round trip. The thread sums are added in a
+// fixed order (a butterfly in each wave, then the waves in turn), so the
+// forces are the same on every run; far pairs add exactly zero, so they are
+// those of the cell list up to the order of the sums. The workgroup writes
+// the sphere's whole accumulator record (zeros, the pair force and the near
+// flag), which takes the place of the record clear of the cell-list path.
 constexpr int kAllPairsMax = 1024;
+constexpr int kPairsPer = kAllPairsMax / PBLOCK;
+static_assert(kPairsPer * PBLOCK == kAllPairsMax, "spheres per thread");
 static_assert(ASTRIDE <= 64, "one lane per accumulator entry");
 __global__ void __launch_bounds__(PBLOCK) k_pairs_all(CellArgs a) {
-  const int p = int(blockIdx.x) * (PBLOCK / 64) + int(threadIdx.x) / 64;
-  if (p >= a.np) return;  // whole waves
-  const int lane = __lane_id();
-  const double* xp = a.ps + size_t(p) * PSTRIDE;
+  const int p = int(blockIdx.x);  // grid: one workgroup per sphere
+  const int t = int(threadIdx.x), lane = __lane_id(), wv = t / 64;
+  const double* rp = a.ps + size_t(p) * PSTRIDE;
+  const double xp[3] = {rp[0], rp[1], rp[2]};
+  double xq[kPairsPer][3];
+#pragma unroll
+  for (int j = 0; j < kPairsPer; ++j) {
+    const int q = t + j * PBLOCK;
+    const double* rq = a.ps + size_t(q < a.np ? q : p) * PSTRIDE;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xq[j][d] = rq[d];
+  }
   double F[3] = {0, 0, 0};
   bool near = false;
-  for (int q = lane; q < a.np; q += 64)
-    if (q != p) pair_term(a, xp, a.ps + size_t(q) * PSTRIDE, F, near);
+#pragma unroll
+  for (int j = 0; j < kPairsPer; ++j) {
+    const int q = t + j * PBLOCK;
+    if (q < a.np && q != p) pair_term(a, xp, rp, xq[j], a.ps + size_t(q) * PSTRIDE, F, near);
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
     for (int e = 0; e < 3; ++e) F[e] += __shfl_xor(F[e], off);
-  near = __ballot(near) != 0ull;
-  wall_term(a, xp, F);
+  const bool wnear = __ballot(near) != 0ull;
+  __shared__ double part[PBLOCK / 64][3];
+  __shared__ int pnear[PBLOCK / 64];
+  if (lane == 0) {
+    for (int e = 0; e < 3; ++e) part[wv][e] = F[e];
+    pnear[wv] = wnear ? 1 : 0;
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  double G[3] = {0, 0, 0};
+  int nr = 0;
+  for (int w = 0; w < PBLOCK / 64; ++w) {
+    for (int e = 0; e < 3; ++e) G[e] += part[w][e];
+    nr |= pnear[w];
+  }
+  wall_term(a, xp, G);
   if (lane < ASTRIDE) {
     double v = 0.0;
-    if (lane == AC_FH) v = F[0];
-    if (lane == AC_FH + 1) v = F[1];
-    if (lane == AC_FH + 2) v = F[2];
-    if (lane == AC_NEAR) v = near ? 1.0 : 0.0;
+    if (lane == AC_FH) v = G[0];
+    if (lane == AC_FH + 1) v = G[1];
+    if (lane == AC_FH + 2) v = G[2];
+    if (lane == AC_NEAR) v = nr ? 1.0 : 0.0;
     a.acc[size_t(p) * ASTRIDE + lane] = v;
   }
 }
@@ -974,8 +1011,7 @@ hipError_t launch_map_update(lb_ctx* c, hipStream_t s) {
   ca.lub_hcap = c->P.lub_hcap;
   hipError_t e;
   if (c->nparticles <= kAllPairsMax) {
-    const int per = PBLOCK / 64;
-    hipLaunchKernelGGL(k_pairs_all, dim3((c->nparticles + per - 1) / per), bp, 0, s, ca);
+    hipLaunchKernelGGL(k_pairs_all, gp, bp, 0, s, ca);
   } else {
     e = launch_zero(pacc(c), size_t(c->nparticles) * ASTRIDE * sizeof(double), s);
     if (e != hipSuccess) return e;
