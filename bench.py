@@ -375,8 +375,10 @@ def stream_probes(gib: float = 8.0, box=(512, 512, 512), reps: int = 10) -> dict
     """The library's streaming probes (lb_probe_stream): hand-written read,
     write and copy kernels over `gib` GiB, and the fused step's access pattern
     (2 x 19 FP32 planes gathered with the D3Q19 pull offsets and stored in
-    place) on a box of the bench's size. GB/s counts the bytes each kernel
-    must move (read + written)."""
+    place) on a box of the bench's size, and the same planes moved by a
+    z-march that also takes the moments in its sweep (the pattern of a step
+    without a separate density pass). GB/s counts the bytes each kernel must
+    move (read + written)."""
     import ctypes as C
     import torch
     from paper_2004_04080_amd import binding as B
@@ -406,6 +408,16 @@ def stream_probes(gib: float = 8.0, box=(512, 512, 512), reps: int = 10) -> dict
     out["collide_pattern"] = {"GBps": round(2 * nb / (ms.value * 1e-3) / 1e9, 1),
                               "bytes": 2 * nb, "ms": round(ms.value, 4),
                               "box": f"{box[0]}x{box[1]}x{box[2]}"}
+    if box[0] % 128 == 0 and box[1] % 8 == 0:
+        # the same planes moved by a z-march that also takes the moments
+        ms = C.c_double()
+        B.check(lib.lb_probe_stream(4, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), nb,
+                                    box[0], box[1], box[2], reps,
+                                    C.c_void_p(stream.cuda_stream), C.byref(ms)),
+                "lb_probe_stream")
+        out["march_pattern"] = {"GBps": round(2 * nb / (ms.value * 1e-3) / 1e9, 1),
+                                "bytes": 2 * nb, "ms": round(ms.value, 4),
+                                "box": f"{box[0]}x{box[1]}x{box[2]}"}
     del a, b
     torch.cuda.empty_cache()
     return out

@@ -357,8 +357,14 @@ int lb_domain_size(struct lb_ctx* ctx, void* work, size_t work_bytes, double* L,
  * two components of 19 FP32 planes of N = nx ny nz nodes in the pattern of
  * the fused step: plane i of node n is gathered from node n - c_i (D3Q19,
  * periodic) of src and stored at n in dst (src and dst each 2*19*N*4 bytes,
- * bytes >= that; one plane below 4 GiB). Device pointers, 16-byte aligned,
- * owned by the caller. One untimed launch, then reps launches on `stream`
+ * bytes >= that; one plane below 4 GiB). kind 4 moves the same planes as a
+ * z-march that also takes the moments in its sweep (the pattern of a step
+ * without a separate density pass, Sec. 3.1): workgroups own 128 x 8 columns
+ * and walk 128 z-planes, gathering each plane for the column and a one-node
+ * ring around it, and store dst_{k,i}(n) = g_{k,i}(n) + 1e-3 sum_{j=1..18} j
+ * s_{1-k}(n + c_j), with g the values kind 3 stores and s_k(m) the sum over i
+ * of g_{k,i}(m); nx a multiple of 128 and ny of 8 (else LB_E_SHAPE). Device
+ * pointers, 16-byte aligned, owned by the caller. One untimed launch, then reps launches on `stream`
  * (hipStream_t) between HIP events; *ms_per_launch gets their mean.
  * Synchronises. Errors: LB_E_ARG, LB_E_SHAPE, LB_E_HIP. */
 int lb_probe_stream(int32_t kind, const void* src, void* dst, size_t bytes, int32_t nx,
