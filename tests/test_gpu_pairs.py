@@ -74,3 +74,46 @@ def test_pair_forces_over_many_cells():
     assert (fh > 0).all(), int((fh == 0).sum())
     assert lat.observables().flags == 0
     lat.close()
+
+
+def test_pair_paths_agree_across_the_all_pairs_threshold():
+    """Up to 1,024 spheres the pair forces come from one kernel over all
+    pairs, above that from the cell list. 512 touching pairs (1,024 spheres,
+    the first path) and the same pairs with a 1,025th sphere far from all of
+    them (the second path) must give the same Hertz and lubrication forces to
+    rounding, and the same map outside the added sphere."""
+    from paper_2004_04080_amd import Lattice, Params
+    x = _pairs(synth.BASE_SEED + 83, npairs=512)
+    L = np.array(SHAPE, dtype=float)
+    extra = None
+    rng = np.random.default_rng(5)
+    while extra is None:
+        c = rng.uniform(0, 1, 3) * L
+        d = x - c
+        d -= L * np.round(d / L)
+        if np.sqrt((d ** 2).sum(1)).min() > 2 * R + 3:
+            extra = c
+    v = np.random.default_rng(6).uniform(-0.01, 0.01, (len(x), 3))
+    w = synth.Workload("pairs2", *SHAPE, seed=synth.BASE_SEED + 84)
+    rho = w.densities()
+
+    def run(xs, vs):
+        p = Params(*SHAPE, G=0.65, precision="fp64", radius=R, particle_density=2.0,
+                   hertz_K=0.01, lub_mu=0.1, max_particles=len(xs))
+        lat = Lattice(p, rho)
+        lat.add_particles(xs, vs)
+        lat.step(1)
+        rec, own = lat.particles(), lat.owner()
+        lat.close()
+        return rec, own
+
+    ra, oa = run(x, v)
+    rb, ob = run(np.vstack([x, extra]), np.vstack([v, np.zeros(3)]))
+    fa, fb = ra[:, 31:34], rb[:len(x), 31:34]
+    scale = np.abs(fa).max()
+    err = np.abs(fb - fa).max() / scale
+    print(f"[pairs] {len(x)} against {len(x) + 1} spheres: pair forces differ by {err:.1e} "
+          f"of max|F_H| = {scale:.2e}", flush=True)
+    assert scale > 0 and err < 1e-13
+    keep = ob != len(x) + 1
+    assert np.array_equal(oa[keep], ob[keep])
