@@ -371,14 +371,15 @@ def copy_probe(gib: float, reps: int = 5) -> dict:
             "GBps_read_plus_write": round(2 * n / (ms.value * 1e-3) / 1e9, 1)}
 
 
-def stream_probes(gib: float = 8.0, box=(512, 512, 512), reps: int = 10) -> dict:
+def stream_probes(gib: float = 8.0, box=(512, 512, 512), reps: int = 10,
+                  march: bool = False) -> dict:
     """The library's streaming probes (lb_probe_stream): hand-written read,
     write and copy kernels over `gib` GiB, and the fused step's access pattern
     (2 x 19 FP32 planes gathered with the D3Q19 pull offsets and stored in
-    place) on a box of the bench's size, and the same planes moved by a
-    z-march that also takes the moments in its sweep (the pattern of a step
-    without a separate density pass). GB/s counts the bytes each kernel must
-    move (read + written)."""
+    place) on a box of the bench's size, and with march=True the same planes
+    moved by a z-march that also takes the moments in its sweep (the pattern
+    of a step without a separate density pass). GB/s counts the bytes each
+    kernel must move (read + written)."""
     import ctypes as C
     import torch
     from paper_2004_04080_amd import binding as B
@@ -408,7 +409,7 @@ def stream_probes(gib: float = 8.0, box=(512, 512, 512), reps: int = 10) -> dict
     out["collide_pattern"] = {"GBps": round(2 * nb / (ms.value * 1e-3) / 1e9, 1),
                               "bytes": 2 * nb, "ms": round(ms.value, 4),
                               "box": f"{box[0]}x{box[1]}x{box[2]}"}
-    if box[0] % 128 == 0 and box[1] % 8 == 0:
+    if march and box[0] % 128 == 0 and box[1] % 8 == 0:
         # the same planes moved by a z-march that also takes the moments
         ms = C.c_double()
         B.check(lib.lb_probe_stream(4, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), nb,
@@ -450,6 +451,9 @@ def main():
                     help="skip the FP64 run (and with it the FP32 accuracy figure)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--march-probe", action="store_true",
+                    help="also time the z-march probe (lb_probe_stream kind 4); not in the "
+                         "default run")
     ap.add_argument("--workloads", default="MT0,C4",
                     help="comma-separated further boxes (C2,C3,C4,MT0) timed after the main "
                          "one and reported under other_workloads (same step counts)")
@@ -512,7 +516,8 @@ def main():
                      want_roofline=True)
         others.append(other_line(wo, ro, es, args.precision, args.steps))
         log(f"[bench] {others[-1]}")
-    probes = None if args.no_probes else stream_probes(box=(w.nx, w.ny, w.nz))
+    probes = None if args.no_probes else stream_probes(box=(w.nx, w.ny, w.nz),
+                                                         march=args.march_probe)
     if probes:
         log(f"[bench] streaming probes: {probes}")
     cpu = None if args.no_cpu_baseline else cpu_baseline()
