@@ -169,3 +169,9 @@ def test_stream_probe_rejects_bad_arguments_on_the_host():
                                C.byref(ms)) == B.LB_E_SHAPE
     assert lib.lb_probe_stream(3, buf, buf, 38 * 4 * 64 - 4, 4, 4, 4, 1, None,
                                C.byref(ms)) == B.LB_E_SHAPE
+    # the march pattern: columns of 128 x 8 nodes must tile the x-y plane
+    big = 38 * 4 * 256 * 16 * 4
+    for nx, ny in ((120, 16), (256, 12), (64, 8)):
+        assert lib.lb_probe_stream(4, buf, buf, big, nx, ny, 4, 1, None,
+                                   C.byref(ms)) == B.LB_E_SHAPE, (nx, ny)
+    assert lib.lb_probe_stream(5, buf, buf, big, 256, 16, 4, 1, None, C.byref(ms)) == B.LB_E_ARG
