@@ -187,3 +187,37 @@ def test_ladd_drag_and_braking_torque_signs():
     o.step(1)
     F = o.particles()[0, O.REC["Fliq"]:O.REC["Fliq"] + 3]
     assert F @ vv[0] < 0
+
+
+def test_resting_solids_in_resting_fluid_feel_no_force_or_torque():
+    """For any finite set of solid nodes, the D3Q19 links from fluid into it
+    satisfy sum w_i c_i = 0 and sum r x w_i c_i = 0: every pair of solid
+    neighbours would contribute a link twice with opposite c_i, and the full
+    stencil has sum_i w_i c_i = 0. In a uniform fluid at rest every link
+    carries 2 w_i rho c_i (plain bounce-back of the equilibrium). So a fixed
+    sphere on its own, also across the periodic seams, feels no force and no
+    torque; two overlapping spheres share their nodes (the lower index takes
+    them), each has only part of the union's links and feels a force, and
+    the two forces and torques about a common point cancel."""
+    L = (26, 22, 24)
+    p = O.Params(*L, ncomp=2, G=0.0, radius=3.7, particles_fixed=True)
+    x = np.array([[5.3, 4.1, 6.9], [9.8, 6.2, 8.0],      # overlapping pair
+                  [25.4, 11.3, 12.6],                     # across the x seam
+                  [14.1, 17.6, 1.2],                      # across the z seam
+                  [18.9, 3.3, 17.7]])
+    o = O.Oracle(p, np.ones((2, p.N)))
+    o.add_particles(x)
+    assert (o.owner() > 0).sum() > 700
+    o.step(1)
+    rec = o.particles()
+    F = rec[:, O.REC["Fliq"]:O.REC["Fliq"] + 3]
+    T = rec[:, O.REC["Tliq"]:O.REC["Tliq"] + 3]
+    scale = rec[:, O.REC["flabs"]].max()
+    assert scale > 1.0
+    tol_f, tol_t = 1e-14 * scale, 1e-13 * scale
+    assert np.abs(F[2:]).max() <= tol_f and np.abs(T[2:]).max() <= tol_t
+    # the overlapping pair: opposite forces, and torques that cancel about one point
+    assert np.abs(F[0]).max() > 1.0
+    assert np.abs(F[0] + F[1]).max() <= tol_f
+    Tc = T[0] + T[1] + np.cross(x[1] - x[0], F[1])     # both torques about x[0]
+    assert np.abs(Tc).max() <= tol_t
